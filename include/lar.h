@@ -1,0 +1,152 @@
+/*
+ * lar.h -- C ABI of the MI355X (gfx950) LArTPC signal-simulation hot path.
+ *
+ * The library computes the signal term of the LArTPC measurement model,
+ * paper arXiv:2203.02479 Sec. 2.1 Eq. (1):  M = R (*) S, per wire plane on
+ * the 2D (drift time x wire pitch) space, with the three tasks named in
+ * Sec. 2.2 -- Raster (bin each diffused ionization group as a Gaussian
+ * patch), Scatter-add (sum the patches into one dense grid, Sec. 2.3) and
+ * Convolution (Sec. 2.2 Eq. (2): FT of the grid, product with the response
+ * spectrum, inverse FT).
+ *
+ * Conventions shared by every call:
+ *  - All array pointers are DEVICE pointers owned by the caller.  Structs
+ *    (lar_plane, lar_depos, lar_fluct) are read from host memory during the
+ *    call only.  `stream` is a hipStream_t (NULL = the null stream).
+ *  - Calls are asynchronous on `stream`, never synchronise, never allocate
+ *    device memory; scratch comes from a caller-provided workspace whose
+ *    size the matching *_workspace() call reports.  The workspace must not
+ *    be used by overlapping calls.
+ *  - Return value: LAR_OK (0) or a negative LAR_E* code; on error nothing
+ *    is launched, except LAR_EHIP (a launch failed; lar_last_hip_error()
+ *    gives the hipError_t).
+ *  - Grid layout: S[m][j], m = w*n_imp + k (impact row k of wire w; row m
+ *    covers pitch [x0 - pitch/2 + m*d, +d) with d = pitch/n_imp), j = tick
+ *    (covers [t0 + j*tick, +tick)); row-major, ticks contiguous,
+ *    n_wires*n_imp rows of n_ticks floats.
+ *  - Response spectrum layout: resp[k][p][f] complex (interleaved re, im
+ *    float32), k < n_imp, p < nw_fft, f <= nt_fft/2: the 2D DFT over
+ *    (nw_fft, nt_fft) of the response of impact offset k.
+ *  - Waveforms: wave[w][j], n_wires rows of n_ticks floats.
+ *  - Units: time and sigma_t in microseconds, x, pitch and sigma_x in mm,
+ *    charge in electrons.
+ */
+#ifndef LAR_H
+#define LAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LAR_OK = 0,
+    LAR_EINVAL = -1,     /* null pointer, negative count, bad enum */
+    LAR_ESIZE = -2,      /* FFT length not 2^a 3^b, too short, or beyond the kernel limits */
+    LAR_EWORKSPACE = -3, /* workspace missing or smaller than required */
+    LAR_EHIP = -4        /* a HIP launch failed; see lar_last_hip_error() */
+};
+
+/* Geometry of one wire plane and its FFT sizes (paper Sec. 2.1: each plane
+ * is simulated on its own drift-time x wire-pitch space).
+ * nt_fft: time FFT length Tf, even, 2^a 3^b, n_ticks <= Tf <= 16384; the
+ *         convolution is circular over Tf (ticks n_ticks..Tf-1 hold zero).
+ * nw_fft: wire FFT length Wf, 2^a 3^b, n_wires <= Wf <= 1024; circular over
+ *         Wf, so Wf >= n_wires + 2H gives a linear convolution for a
+ *         response spanning +-H wires. */
+typedef struct lar_plane {
+    int32_t n_wires;
+    int32_t n_imp;      /* impact positions per pitch, >= 1 */
+    int32_t n_ticks;
+    int32_t nt_fft;
+    int32_t nw_fft;
+    float pitch;        /* wire pitch (mm) */
+    float x0;           /* pitch coordinate of wire 0's centre (mm) */
+    float tick;         /* sampling period (us) */
+    float t0;           /* start time of tick 0 (us) */
+} lar_plane;
+
+/* Drifted, diffused depositions as a structure of arrays (paper Sec. 2.3:
+ * SoA data objects, parallel over ionization groups).  n >= 0 entries each;
+ * sigma_t is the longitudinal width in time units.  A depo with any
+ * non-finite field is skipped; sigma < 1e-6 bin widths is a point charge. */
+typedef struct lar_depos {
+    const float *q, *t, *x, *sigma_t, *sigma_x;
+    int64_t n;
+} lar_depos;
+
+/* Charge fluctuation (paper Sec. 3.1: the reference code draws binomial
+ * electron counts).  mode 0: mean patch q*wt*wx; 1: Binomial(rint|q|, p)
+ * per bin; 2: Poisson(|q| p) per bin; p = wt*wx, sign(q) restored.  Draws
+ * use Philox4x32-10 with key = seed and counter (depo index, event,
+ * m*n_ticks + j, plane*2^24 + draw), so results are reproducible for any
+ * launch shape.  NULL = mode 0. */
+typedef struct lar_fluct {
+    int32_t mode;
+    uint32_t event;
+    uint32_t plane;
+    uint32_t reserved;
+    uint64_t seed;
+} lar_fluct;
+
+const char *lar_status_str(int status);
+int lar_last_hip_error(void);
+
+/* Raster + scatter-add (paper Sec. 2.2 "Raster" and "Scatter-add").  For
+ * every depo: the bins intersecting mu +- nsigma*sigma on each axis, the
+ * Gaussian bin integrals Phi(z_{j+1}) - Phi(z_j) (no renormalisation), the
+ * patch q*wt[j]*wx[m] (or its fluctuated counts) ADDED into grid.
+ * grid: [n_wires*n_imp][n_ticks] float, accumulated (+=), not cleared.
+ * nsigma > 0.  Uses no workspace.  Float atomics: the summation order, and
+ * so the last bits of the grid, depend on scheduling. */
+int lar_raster(const lar_plane *plane, const lar_depos *depos, float nsigma,
+               const lar_fluct *fluct, float *grid, void *stream);
+
+/* Convolution of a grid with the response spectra (paper Sec. 2.2 Eq. (2)):
+ * wave = crop_{n_wires x n_ticks} IFT2( sum_k resp[k] * FT2(S_k) ), where
+ * S_k[w][j] = grid[w*n_imp + k][j] zero-padded to (nw_fft, nt_fft), FT2 is
+ * a real FFT over time then a complex FFT over wires (unnormalised), and
+ * IFT2 the inverse (1/(nw_fft*nt_fft)) whose real inverse in time takes the
+ * real part of the DC and Nyquist columns.  wave is overwritten. */
+int lar_fftconv_workspace(const lar_plane *plane, size_t *bytes);
+int lar_fftconv(const lar_plane *plane, const float *grid, const float *resp, float *wave,
+                void *workspace, size_t ws_bytes, void *stream);
+
+/* One plane end to end: clear an internal grid, lar_raster, lar_fftconv. */
+int lar_sim_plane_workspace(const lar_plane *plane, size_t *bytes);
+int lar_sim_plane(const lar_plane *plane, const lar_depos *depos, float nsigma,
+                  const lar_fluct *fluct, const float *resp, float *wave,
+                  void *workspace, size_t ws_bytes, void *stream);
+
+/* Response spectrum from a time-domain response (detector response R of
+ * Eq. (1), paper Sec. 2.1): r_time[k][dw + half_w][tau], k < n_imp,
+ * |dw| <= half_w, tau < n_rt, placed at wire index dw mod nw_fft and tick
+ * tau, then resp = FT2 (as in lar_fftconv).  resp is overwritten. */
+int lar_response_spectrum_workspace(const lar_plane *plane, int32_t half_w, int32_t n_rt,
+                                    size_t *bytes);
+int lar_response_spectrum(const lar_plane *plane, const float *r_time, int32_t half_w,
+                          int32_t n_rt, float *resp, void *workspace, size_t ws_bytes,
+                          void *stream);
+
+/* The per-bin sampler of lar_raster on injected inputs (same device code):
+ * out[i] = sign(q[i]) * n with n ~ Binomial(rint|q[i]|, p[i]) (mode 1) or
+ * Poisson(|q[i]| p[i]) (mode 2), counter (ctr3[3i], ctr3[3i+1], ctr3[3i+2],
+ * plane*2^24 + draw), key = seed.  p is double (the sampler's precision). */
+int lar_sample_counts(int32_t mode, int64_t n, const float *q, const double *p,
+                      const uint32_t *ctr3, uint32_t plane, uint64_t seed, float *out,
+                      void *stream);
+
+/* Profiling aid (no paper counterpart): when events is non-NULL, the calls
+ * on this host thread record events[i] (each a hipEvent_t created by the
+ * caller) on their stream right after kernel stage i: 0 grid clear,
+ * 1 raster, 2 time-axis real FFT, 3 wire pass, 4 time-axis inverse real FFT
+ * (lar_fftconv records 2..4, lar_raster 1).  n_events must be >= 5; pass
+ * NULL to stop.  Recording adds no synchronisation. */
+int lar_set_stage_events(void *const *events, int32_t n_events);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAR_H */

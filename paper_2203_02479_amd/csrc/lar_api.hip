@@ -1,0 +1,248 @@
+// lar_api.hip -- host implementation of the C ABI declared in include/lar.h.
+// Argument checks, workspace layout, kernel sequencing.  Everything is
+// asynchronous on the caller's stream; nothing here allocates or syncs.
+#include <limits.h>
+#include <math.h>
+
+#include "lar_internal.hpp"
+
+using namespace lar;
+
+static thread_local int g_last_hip = 0;
+static thread_local hipEvent_t g_stage_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+
+static hipError_t stage_mark(int i, hipStream_t s) {
+    return g_stage_ev[i] ? hipEventRecord(g_stage_ev[i], s) : hipSuccess;
+}
+
+static int hip_status(hipError_t e) {
+    if (e == hipSuccess) return LAR_OK;
+    g_last_hip = (int)e;
+    return LAR_EHIP;
+}
+
+#define LAR_TRY(expr)                          \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return hip_status(_e); \
+    } while (0)
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Row pitch (complex elements) of the internal time-spectrum buffers: the
+// half spectrum padded to a multiple of 16 so rows start on 128-byte lines.
+static int64_t spec_ld(const lar_plane* p) { return ((int64_t)(p->nt_fft / 2 + 1) + 15) / 16 * 16; }
+
+static bool smooth(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+static int check_plane(const lar_plane* p) {
+    if (!p) return LAR_EINVAL;
+    if (p->n_wires < 1 || p->n_imp < 1 || p->n_ticks < 1) return LAR_EINVAL;
+    if (!(p->tick > 0.f) || !(p->pitch > 0.f) || !isfinite(p->x0) || !isfinite(p->t0))
+        return LAR_EINVAL;
+    if ((int64_t)p->n_wires * p->n_imp > INT_MAX / 2) return LAR_ESIZE;
+    return LAR_OK;
+}
+
+static int check_fft(const lar_plane* p) {
+    int st = check_plane(p);
+    if (st) return st;
+    if (p->nt_fft % 2 || !smooth(p->nt_fft / 2) || p->nt_fft < p->n_ticks || p->nt_fft > 16384)
+        return LAR_ESIZE;
+    if (!smooth(p->nw_fft) || p->nw_fft < p->n_wires || p->nw_fft > 1024) return LAR_ESIZE;
+    return LAR_OK;
+}
+
+static int check_depos(const lar_depos* d) {
+    if (!d || d->n < 0) return LAR_EINVAL;
+    if (d->n > 0 && (!d->q || !d->t || !d->x || !d->sigma_t || !d->sigma_x)) return LAR_EINVAL;
+    if (d->n > (int64_t)UINT32_MAX) return LAR_ESIZE;   // depo index is one counter word
+    return LAR_OK;
+}
+
+static int check_fluct(const lar_fluct* f) {
+    if (!f) return LAR_OK;
+    if (f->mode < 0 || f->mode > 2) return LAR_EINVAL;
+    if (f->plane >= 256u) return LAR_EINVAL;              // plane * 2^24 must fit one word
+    return LAR_OK;
+}
+
+extern "C" {
+
+const char* lar_status_str(int s) {
+    switch (s) {
+        case LAR_OK: return "ok";
+        case LAR_EINVAL: return "invalid argument";
+        case LAR_ESIZE: return "unsupported size";
+        case LAR_EWORKSPACE: return "workspace missing or too small";
+        case LAR_EHIP: return "HIP launch failed";
+        default: return "unknown status";
+    }
+}
+
+int lar_last_hip_error(void) { return g_last_hip; }
+
+int lar_set_stage_events(void* const* events, int32_t n_events) {
+    if (!events) {
+        for (int i = 0; i < 5; ++i) g_stage_ev[i] = nullptr;
+        return LAR_OK;
+    }
+    if (n_events < 5) return LAR_EINVAL;
+    for (int i = 0; i < 5; ++i)
+        if (!events[i]) return LAR_EINVAL;
+    for (int i = 0; i < 5; ++i) g_stage_ev[i] = (hipEvent_t)events[i];
+    return LAR_OK;
+}
+
+int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, const lar_fluct* fluct,
+               float* grid, void* stream) {
+    int st;
+    if ((st = check_plane(plane))) return st;
+    if ((st = check_depos(depos))) return st;
+    if ((st = check_fluct(fluct))) return st;
+    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    if (depos->n == 0) return LAR_OK;
+    if (!grid) return LAR_EINVAL;
+    RasterArgs a;
+    a.n_ticks = plane->n_ticks;
+    a.n_rows = plane->n_wires * plane->n_imp;
+    a.ld = plane->n_ticks;
+    a.org_t = (double)plane->t0;
+    a.wd_t = (double)plane->tick;
+    a.org_x = (double)plane->x0 - (double)plane->pitch / 2.0;
+    a.wd_x = (double)plane->pitch / (double)plane->n_imp;
+    a.nsig = (double)nsigma;
+    a.mode = fluct ? fluct->mode : 0;
+    a.event = fluct ? fluct->event : 0u;
+    a.plane = fluct ? fluct->plane : 0u;
+    a.seed = fluct ? fluct->seed : 0ull;
+    LAR_TRY(launch_raster(a, depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x,
+                          depos->n, grid, (hipStream_t)stream));
+    LAR_TRY(stage_mark(1, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+// fftconv workspace: [spectrum of grid rows: R_rows x ld][wire-pass output: N_w x ld]
+static size_t fftconv_bytes(const lar_plane* p) {
+    size_t ld = (size_t)spec_ld(p);
+    size_t a = align_up((size_t)p->n_wires * p->n_imp * ld * sizeof(float2), 256);
+    size_t b = align_up((size_t)p->n_wires * ld * sizeof(float2), 256);
+    return a + b;
+}
+
+int lar_fftconv_workspace(const lar_plane* plane, size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = fftconv_bytes(plane);
+    return LAR_OK;
+}
+
+static int fftconv_impl(const lar_plane* p, const float* grid, const float* resp, float* wave,
+                        void* ws, hipStream_t s) {
+    const int64_t ld = spec_ld(p);
+    const int rows = p->n_wires * p->n_imp;
+    const int F = p->nt_fft / 2 + 1;
+    float2* Sh = reinterpret_cast<float2*>(ws);
+    float2* Mh = reinterpret_cast<float2*>(
+        reinterpret_cast<char*>(ws) + align_up((size_t)rows * ld * sizeof(float2), 256));
+    LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sh, ld, s));
+    LAR_TRY(stage_mark(2, s));
+    LAR_TRY(launch_wire_fused(Sh, ld, p->n_wires, p->n_imp, p->nw_fft, F,
+                              reinterpret_cast<const float2*>(resp), Mh, ld, s));
+    LAR_TRY(stage_mark(3, s));
+    const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
+    LAR_TRY(launch_c2r_rows(Mh, ld, p->n_wires, p->nt_fft, wave, p->n_ticks, p->n_ticks, scale, s));
+    LAR_TRY(stage_mark(4, s));
+    return LAR_OK;
+}
+
+int lar_fftconv(const lar_plane* plane, const float* grid, const float* resp, float* wave,
+                void* ws, size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!grid || !resp || !wave) return LAR_EINVAL;
+    if (!ws || ws_bytes < fftconv_bytes(plane)) return LAR_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    return fftconv_impl(plane, grid, resp, wave, ws, (hipStream_t)stream);
+}
+
+// sim_plane workspace: [grid: R_rows x n_ticks floats][fftconv workspace]
+static size_t grid_bytes(const lar_plane* p) {
+    return align_up((size_t)p->n_wires * p->n_imp * p->n_ticks * sizeof(float), 256);
+}
+
+int lar_sim_plane_workspace(const lar_plane* plane, size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = grid_bytes(plane) + fftconv_bytes(plane);
+    return LAR_OK;
+}
+
+int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
+                  const lar_fluct* fluct, const float* resp, float* wave, void* ws,
+                  size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if ((st = check_depos(depos))) return st;
+    if ((st = check_fluct(fluct))) return st;
+    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    if (!resp || !wave) return LAR_EINVAL;
+    size_t need = grid_bytes(plane) + fftconv_bytes(plane);
+    if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    float* grid = reinterpret_cast<float*>(ws);
+    LAR_TRY(launch_fill(grid, (int64_t)plane->n_wires * plane->n_imp * plane->n_ticks, s));
+    LAR_TRY(stage_mark(0, s));
+    if ((st = lar_raster(plane, depos, nsigma, fluct, grid, stream))) return st;
+    return fftconv_impl(plane, grid, resp, wave, reinterpret_cast<char*>(ws) + grid_bytes(plane), s);
+}
+
+// response spectrum workspace: time spectra of the n_imp*(2H+1) response rows
+static size_t respspec_bytes(const lar_plane* p, int half_w) {
+    return align_up((size_t)p->n_imp * (2 * half_w + 1) * spec_ld(p) * sizeof(float2), 256);
+}
+
+int lar_response_spectrum_workspace(const lar_plane* plane, int32_t half_w, int32_t n_rt,
+                                    size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (half_w < 0 || n_rt < 1 || n_rt > plane->nt_fft || !bytes) return LAR_EINVAL;
+    *bytes = respspec_bytes(plane, half_w);
+    return LAR_OK;
+}
+
+int lar_response_spectrum(const lar_plane* plane, const float* r_time, int32_t half_w,
+                          int32_t n_rt, float* resp, void* ws, size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (half_w < 0 || n_rt < 1 || n_rt > plane->nt_fft || !r_time || !resp) return LAR_EINVAL;
+    if (!ws || ws_bytes < respspec_bytes(plane, half_w) || reinterpret_cast<uintptr_t>(ws) % 256)
+        return LAR_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int nrw = 2 * half_w + 1;
+    const int64_t ld = spec_ld(plane);
+    float2* rows = reinterpret_cast<float2*>(ws);
+    LAR_TRY(launch_r2c_rows(r_time, n_rt, n_rt, plane->n_imp * nrw, plane->nt_fft, rows, ld, s));
+    LAR_TRY(launch_wire_spectrum(rows, ld, plane->n_imp, nrw, half_w, plane->nw_fft,
+                                 plane->nt_fft / 2 + 1, reinterpret_cast<float2*>(resp), s));
+    return LAR_OK;
+}
+
+int lar_sample_counts(int32_t mode, int64_t n, const float* q, const double* p,
+                      const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
+                      void* stream) {
+    if (mode < 1 || mode > 2 || n < 0 || plane >= 256u) return LAR_EINVAL;
+    if (n == 0) return LAR_OK;
+    if (!q || !p || !ctr3 || !out) return LAR_EINVAL;
+    LAR_TRY(launch_sample_counts(mode, n, q, p, ctr3, plane, seed, out, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// lar_internal.hpp -- device helpers and launcher declarations of the gfx950
+// LArTPC signal-simulation library.  Not part of the public ABI (lar.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lar.h"
+
+namespace lar {
+
+// ---------------------------------------------------------------- FFT plan
+//
+// Mixed-radix Stockham autosort FFT (Stockham 1966; the formulation of Van
+// Loan, "Computational Frameworks for the FFT", 1992): pass p with radix R
+// and sub-transform size Ns (product of earlier radices) reads the R inputs
+// of butterfly j at stride n/R, applies the twiddles exp(-+2 pi i r (j mod Ns)
+// / (Ns R)), and writes the R outputs at (j div Ns) Ns R + (j mod Ns) + r Ns.
+// Lengths are 2^a 3^b; passes use radix 4 first, then 3, then one 2.
+constexpr int kMaxPasses = 16;
+
+struct FftPlan {
+    int n;
+    int npass;
+    int radix[kMaxPasses];
+};
+
+// Host: build the plan for length n; false if n is not 2^a 3^b (n >= 1).
+bool make_plan(int n, FftPlan* plan);
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// Small DFTs, sign -1 (forward) or +1 (inverse) in the exponent.
+template <int R>
+__device__ __forceinline__ void dft_small(float2* v, bool inv);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(float2* v, bool) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<3>(float2* v, bool inv) {
+    const float s3 = 0.86602540378443865f;   // sin(2 pi / 3)
+    float2 t1 = cadd(v[1], v[2]);
+    float2 d = csub(v[1], v[2]);
+    float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    // forward: y1 = t2 - i s3 d, y2 = t2 + i s3 d; inverse swaps the signs
+    float sx = inv ? -s3 : s3;
+    float2 id = make_float2(sx * d.y, -sx * d.x);   // -i * sx * d
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, id);
+    v[2] = csub(t2, id);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(float2* v, bool inv) {
+    float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    float2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    // forward: y1 = a1 - i b1, y3 = a1 + i b1
+    float2 mib1 = inv ? make_float2(-b1.y, b1.x) : make_float2(b1.y, -b1.x);
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, mib1);
+    v[3] = csub(a1, mib1);
+}
+
+// Twiddle accessors: tw(m) = exp(-2 pi i m / n) for 0 <= m < n.
+struct TwFull {           // table of n entries
+    const float2* t;
+    __device__ __forceinline__ float2 operator()(int m) const { return t[m]; }
+};
+struct TwHalf {           // table h[k] = exp(-pi i k / n), k < n (half-angle table)
+    const float2* t;
+    int n;
+    __device__ __forceinline__ float2 operator()(int m) const {
+        int i = 2 * m;
+        if (i < n) return t[i];
+        float2 v = t[i - n];
+        return make_float2(-v.x, -v.y);
+    }
+};
+
+// One Stockham pass over NS interleaved sequences held in LDS (element i of
+// sequence s at A[i*NS + s]).  All loads of a thread happen before the
+// barrier and all stores after it, so the pass is in place.
+template <int R, int MAXB, int NS, class TW>
+__device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid, int T,
+                                              const TW& tw, bool inv) {
+    const int nb = n / R;
+    const int total = nb * NS;
+    const int stride = n / (Ns * R);
+    float2 v[MAXB][R];
+    int dst[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        int w = tid + b * T;
+        dst[b] = -1;
+        if (w < total) {
+            int s = w % NS, j = w / NS;
+            int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = A[(j + r * nb) * NS + s];
+                if (r > 0) {
+                    float2 t = tw(r * k * stride);
+                    x = inv ? cmulc(x, t) : cmul(x, t);
+                }
+                v[b][r] = x;
+            }
+            dst[b] = ((j - k) * R + k) * NS + s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        if (dst[b] >= 0) {
+            dft_small<R>(v[b], inv);
+#pragma unroll
+            for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * NS] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of NS interleaved length-n sequences in LDS by T threads,
+// VPT >= n*NS/T values per thread.  Unnormalised; inv selects exp(+...).
+template <int VPT, int NS, class TW>
+__device__ __forceinline__ void fft_lds(float2* A, const FftPlan& plan, int tid, int T,
+                                        const TW& tw, bool inv) {
+    int Ns = 1;
+    for (int p = 0; p < plan.npass; ++p) {
+        int R = plan.radix[p];
+        if (R == 4)
+            stockham_pass<4, (VPT + 3) / 4, NS>(A, plan.n, Ns, tid, T, tw, inv);
+        else if (R == 3)
+            stockham_pass<3, (VPT + 2) / 3, NS>(A, plan.n, Ns, tid, T, tw, inv);
+        else
+            stockham_pass<2, (VPT + 1) / 2, NS>(A, plan.n, Ns, tid, T, tw, inv);
+        Ns *= R;
+    }
+}
+
+// blockIdx -> tile with consecutive tiles on one XCD (workgroups are dealt
+// round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    int x = b & 7, idx = b >> 3;
+    int per = G >> 3, rem = G & 7;
+    return x * per + min(x, rem) + idx;
+}
+
+// ---------------------------------------------------------------- launchers
+int device_cus();   // compute units of the current device (cached)
+
+hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
+                           float2* out, int64_t ld_out, hipStream_t s);
+hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
+                           int64_t ld_out, int n_out, float scale, hipStream_t s);
+hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
+                             int F, const float2* R, float2* M, int64_t ldM, hipStream_t s);
+hipError_t launch_wire_spectrum(const float2* rows, int64_t ld_rows, int n_imp, int nrw,
+                                int half_w, int nw_fft, int F, float2* resp, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, hipStream_t s);
+
+struct RasterArgs {
+    int n_ticks, n_rows;
+    int64_t ld;
+    double org_t, wd_t, org_x, wd_x, nsig;
+    int mode;
+    uint32_t event, plane;
+    uint64_t seed;
+};
+hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
+                         const float* st, const float* sx, int64_t n, float* grid, hipStream_t s);
+hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
+                                const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
+                                hipStream_t s);
+
+}  // namespace lar

@@ -1,0 +1,226 @@
+"""ctypes binding of the gfx950 library ``liblar.so`` (C ABI in include/lar.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Arrays are torch tensors on the GPU (device
+pointers are passed through); the stream is the caller's current HIP stream
+unless one is given.  There is no CPU fallback: if the library is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblar.so")
+
+LAR_OK, LAR_EINVAL, LAR_ESIZE, LAR_EWORKSPACE, LAR_EHIP = 0, -1, -2, -3, -4
+
+
+class LarError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {_lib().lar_status_str(status).decode()} (status {status}"
+                         + (f", hip error {_lib().lar_last_hip_error()})" if status == LAR_EHIP else ")"))
+
+
+class lar_plane(ctypes.Structure):
+    _fields_ = [("n_wires", ctypes.c_int32), ("n_imp", ctypes.c_int32), ("n_ticks", ctypes.c_int32),
+                ("nt_fft", ctypes.c_int32), ("nw_fft", ctypes.c_int32), ("pitch", ctypes.c_float),
+                ("x0", ctypes.c_float), ("tick", ctypes.c_float), ("t0", ctypes.c_float)]
+
+
+class lar_depos(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p), ("t", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("sigma_t", ctypes.c_void_p), ("sigma_x", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class lar_fluct(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("event", ctypes.c_uint32), ("plane", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+# name -> (argtypes, restype); every symbol declared in include/lar.h
+_P, _VP, _SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
+SIGNATURES = {
+    "lar_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "lar_last_hip_error": ([], ctypes.c_int),
+    "lar_raster": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP], ctypes.c_int),
+    "lar_fftconv_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_fftconv": ([_P(lar_plane), _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
+    "lar_sim_plane_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_sim_plane": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP, _VP, _SZ,
+                       _VP], ctypes.c_int),
+    "lar_response_spectrum_workspace": ([_P(lar_plane), ctypes.c_int32, ctypes.c_int32, _P(_SZ)],
+                                        ctypes.c_int),
+    "lar_response_spectrum": ([_P(lar_plane), _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _SZ, _VP],
+                              ctypes.c_int),
+    "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
+    "lar_sample_counts": ([ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.c_uint64,
+                           _VP, _VP], ctypes.c_int),
+}
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2203_02479_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def lib():
+    return _lib()
+
+
+def _check(status, what):
+    if status != LAR_OK:
+        raise LarError(status, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_plane(p) -> lar_plane:
+    """lar_plane from any object with the geometry attributes (e.g. inputs.Plane)."""
+    return lar_plane(int(p.n_wires), int(p.n_imp), int(p.n_ticks), int(p.nt_fft), int(p.nw_fft),
+                     float(p.pitch), float(p.x0), float(p.tick), float(p.t0))
+
+
+class DeviceDepos:
+    """Depositions resident on the GPU as five float32 tensors (SoA)."""
+
+    def __init__(self, q, t, x, sigma_t, sigma_x):
+        self.q, self.t, self.x, self.sigma_t, self.sigma_x = q, t, x, sigma_t, sigma_x
+        n = q.numel()
+        for a in (q, t, x, sigma_t, sigma_x):
+            if a.dtype != torch.float32 or a.numel() != n or not a.is_cuda:
+                raise TypeError("five float32 device tensors of equal length expected")
+
+    @classmethod
+    def from_host(cls, depos, device="cuda"):
+        return cls(*(torch.as_tensor(a, dtype=torch.float32).to(device).contiguous() for a in depos.arrays()))
+
+    def __len__(self):
+        return self.q.numel()
+
+    def struct(self) -> lar_depos:
+        n = self.q.numel()
+        if n == 0:
+            return lar_depos(None, None, None, None, None, 0)
+        return lar_depos(*(a.data_ptr() for a in (self.q, self.t, self.x, self.sigma_t, self.sigma_x)), n)
+
+
+def _fluct(fluct):
+    if fluct is None:
+        return None
+    if isinstance(fluct, lar_fluct):
+        return ctypes.byref(fluct)
+    mode, seed, event, plane = fluct
+    return ctypes.byref(lar_fluct(int(mode), int(event), int(plane), 0, int(seed)))
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- calls
+
+def raster(plane, depos: DeviceDepos, nsigma, fluct, grid, stream=None):
+    pl = make_plane(plane)
+    ds = depos.struct()
+    _check(_lib().lar_raster(ctypes.byref(pl), ctypes.byref(ds), float(nsigma), _fluct(fluct), _ptr(grid),
+                             _stream(stream)), "lar_raster")
+
+
+def fftconv_workspace(plane) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_fftconv_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)),
+           "lar_fftconv_workspace")
+    return n.value
+
+
+def fftconv(plane, grid, resp, wave, ws, stream=None):
+    pl = make_plane(plane)
+    _check(_lib().lar_fftconv(ctypes.byref(pl), _ptr(grid), _ptr(resp), _ptr(wave), _ptr(ws), ws.numel(),
+                              _stream(stream)), "lar_fftconv")
+
+
+def sim_plane_workspace(plane) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_sim_plane_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)),
+           "lar_sim_plane_workspace")
+    return n.value
+
+
+def sim_plane(plane, depos: DeviceDepos, nsigma, fluct, resp, wave, ws, stream=None):
+    pl = make_plane(plane)
+    ds = depos.struct()
+    _check(_lib().lar_sim_plane(ctypes.byref(pl), ctypes.byref(ds), float(nsigma), _fluct(fluct), _ptr(resp),
+                                _ptr(wave), _ptr(ws), ws.numel(), _stream(stream)), "lar_sim_plane")
+
+
+def response_spectrum_workspace(plane, half_w, n_rt) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_response_spectrum_workspace(ctypes.byref(make_plane(plane)), int(half_w), int(n_rt),
+                                                  ctypes.byref(n)), "lar_response_spectrum_workspace")
+    return n.value
+
+
+def response_spectrum(plane, r_time, half_w, n_rt, resp, ws, stream=None):
+    pl = make_plane(plane)
+    _check(_lib().lar_response_spectrum(ctypes.byref(pl), _ptr(r_time), int(half_w), int(n_rt), _ptr(resp),
+                                        _ptr(ws), ws.numel(), _stream(stream)), "lar_response_spectrum")
+
+
+def sample_counts(mode, q, p, ctr3, plane_id, seed, out, stream=None):
+    n = q.numel()
+    _check(_lib().lar_sample_counts(int(mode), n, _ptr(q), _ptr(p), _ptr(ctr3), int(plane_id), int(seed),
+                                    _ptr(out), _stream(stream)), "lar_sample_counts")
+
+
+# ---------------------------------------------------------------- conveniences
+
+def spectrum_from_time(plane, r_time_np, device="cuda"):
+    """Response spectrum [n_imp][Wf][F][2] float32 on the device from a
+    time-domain response [n_imp][2H+1][L] (numpy)."""
+    r = torch.as_tensor(r_time_np, dtype=torch.float32).to(device).contiguous()
+    n_imp, nrw, L = r.shape
+    H = (nrw - 1) // 2
+    resp = torch.empty((plane.n_imp, plane.nw_fft, plane.nt_fft // 2 + 1, 2), dtype=torch.float32, device=device)
+    ws = workspace(response_spectrum_workspace(plane, H, L), device)
+    response_spectrum(plane, r, H, L, resp, ws)
+    return resp
+
+
+def set_stage_events(events):
+    """Record the given torch.cuda.Event objects (5) after each kernel stage
+    of lar_sim_plane / lar_fftconv on this thread; None to stop."""
+    if events is None:
+        _check(_lib().lar_set_stage_events(None, 0), "lar_set_stage_events")
+        return
+    arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+    _check(_lib().lar_set_stage_events(arr, len(events)), "lar_set_stage_events")
