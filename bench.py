@@ -69,9 +69,9 @@ def main():
     r = inputs.response_time(P.n_imp, P.half_w, inputs.RESP_TICKS, P.kind)
     D = lar.DeviceDepos.from_host(dep)
     resp = lar.spectrum_from_time(P, r)
-    ws = lar.workspace(lar.sim_plane_workspace(P))
-    wave = torch.empty((P.n_wires, P.n_ticks), dtype=torch.float32, device="cuda")
     seed = inputs.SEED0 + 100
+    ws = lar.workspace(lar.sim_plane_workspace(P, n_depo, (args.fluct, seed, 0, 2) if args.fluct else None))
+    wave = torch.empty((P.n_wires, P.n_ticks), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
     def step(i):

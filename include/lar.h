@@ -99,10 +99,21 @@ int lar_last_hip_error(void);
  * Gaussian bin integrals Phi(z_{j+1}) - Phi(z_j) (no renormalisation), the
  * patch q*wt[j]*wx[m] (or its fluctuated counts) ADDED into grid.
  * grid: [n_wires*n_imp][n_ticks] float, accumulated (+=), not cleared.
- * nsigma > 0.  Uses no workspace.  Float atomics: the summation order, and
- * so the last bits of the grid, depend on scheduling. */
+ * nsigma > 0.  Float atomics: the summation order, and so the last bits of
+ * the grid, depend on scheduling (fluctuated counts are integers and sum
+ * exactly below 2^24).
+ * Workspace: none for the mean patch (ws may be NULL); a fluctuated raster
+ * queues the bins that need the full rejection samplers in it.
+ * lar_raster_workspace gives the recommended size for n_depos; any size of
+ * at least the size it gives for n_depos = depos->n with a queue of zero
+ * (the sum of a 256-byte header and one byte per 16 depos, rounded up to
+ * 256) is accepted and gives the same counts, a smaller queue only moves
+ * work to a slower path.  The workspace must be 256-byte aligned. */
+int lar_raster_workspace(const lar_plane *plane, int64_t n_depos, const lar_fluct *fluct,
+                         size_t *bytes);
 int lar_raster(const lar_plane *plane, const lar_depos *depos, float nsigma,
-               const lar_fluct *fluct, float *grid, void *stream);
+               const lar_fluct *fluct, float *grid, void *workspace, size_t ws_bytes,
+               void *stream);
 
 /* Convolution of a grid with the response spectra (paper Sec. 2.2 Eq. (2)):
  * wave = crop_{n_wires x n_ticks} IFT2( sum_k resp[k] * FT2(S_k) ), where
@@ -114,8 +125,11 @@ int lar_fftconv_workspace(const lar_plane *plane, size_t *bytes);
 int lar_fftconv(const lar_plane *plane, const float *grid, const float *resp, float *wave,
                 void *workspace, size_t ws_bytes, void *stream);
 
-/* One plane end to end: clear an internal grid, lar_raster, lar_fftconv. */
-int lar_sim_plane_workspace(const lar_plane *plane, size_t *bytes);
+/* One plane end to end: clear an internal grid, lar_raster, lar_fftconv.
+ * The workspace covers the grid, the raster's queue for n_depos depos and
+ * the convolution's buffers. */
+int lar_sim_plane_workspace(const lar_plane *plane, int64_t n_depos, const lar_fluct *fluct,
+                            size_t *bytes);
 int lar_sim_plane(const lar_plane *plane, const lar_depos *depos, float nsigma,
                   const lar_fluct *fluct, const float *resp, float *wave,
                   void *workspace, size_t ws_bytes, void *stream);

@@ -238,13 +238,28 @@ static double lo_fc(double k)
     return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0) * r2) * r2) * r;
 }
 
-/* Binomial(n, p) by sequential inversion from k = 0 (p <= 1/2, n*p < 10). */
+/* x^n for a non-negative integer n (held in a double) by binary powering:
+ * square-and-multiply over the bits of n from the least significant. */
+static double lo_ipow(double x, double n)
+{
+    uint64_t e = (uint64_t)n;
+    double r = 1.0, b = x;
+    while (e) {
+        if (e & 1u) r = r * b;
+        e >>= 1;
+        if (e) b = b * b;
+    }
+    return r;
+}
+
+/* Binomial(n, p) by sequential inversion from k = 0 (p <= 1/2, n*p < 10):
+ * f(0) = (1-p)^n, f(k) = f(k-1) * ((n+1) r / k - r) with r = p/(1-p). */
 static double lo_binom_inv(double n, double p, lo_stream *s)
 {
     double q = 1.0 - p;
     double ratio = p / q;
     double g = ratio * (n + 1.0);
-    double f0 = exp(n * log1p(-p));
+    double f0 = lo_ipow(q, n);
     for (int tries = 0; tries < LO_MAX_TRIES; ++tries) {
         double u = lo_uniform(s);
         double f = f0;

@@ -41,7 +41,6 @@ int device_cus() {
     return cus[dev];
 }
 
-static constexpr int kRowThreads = 256;
 
 // Half-angle table h[k] = exp(-pi i k / Nh) = exp(-2 pi i k / Tf), k < Nh,
 // computed in double and rounded once.
@@ -53,8 +52,34 @@ __device__ __forceinline__ void fill_half_table(float2* h, int Nh, int tid, int 
     }
 }
 
+// Even/odd sample pairs of one row into registers: pair n = tid + i*T.
+// Loads are unconditional (addresses clamped into the row) so that the
+// whole row is in flight at once.
 template <int VPT>
-__global__ __launch_bounds__(kRowThreads) void k_r2c_rows(const float* __restrict__ in,
+__device__ __forceinline__ void load_row_pairs(const float* __restrict__ x, int n_in, int Nh,
+                                               int tid, int T, bool pairs_ok, float2 (&v)[VPT]) {
+    if (pairs_ok) {
+        const float2* x2 = reinterpret_cast<const float2*>(x);
+        const int full = n_in >> 1;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int n = tid + i * T;
+            float2 a = x2[min(n, max(full - 1, 0))];
+            float tail = x[min(2 * n, n_in - 1)];
+            v[i] = n < full ? a : make_float2(2 * n < n_in ? tail : 0.f, 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int n = tid + i * T;
+            float a = x[min(2 * n, n_in - 1)], b = x[min(2 * n + 1, n_in - 1)];
+            v[i] = make_float2(2 * n < n_in ? a : 0.f, 2 * n + 1 < n_in ? b : 0.f);
+        }
+    }
+}
+
+template <int VPT, int NT>
+__global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
                                                           int64_t ld_in, int n_in, int nrows,
                                                           FftPlan plan, float2* __restrict__ out,
                                                           int64_t ld_out, int pairs_ok) {
@@ -64,25 +89,20 @@ __global__ __launch_bounds__(kRowThreads) void k_r2c_rows(const float* __restric
     float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
     const TwHalf tw{h, Nh};
-    for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
-        const float* x = in + (int64_t)row * ld_in;
-        __syncthreads();
-        if (pairs_ok) {
-            const float2* x2 = reinterpret_cast<const float2*>(x);
-            const int full = n_in >> 1;
-            for (int n = tid; n < Nh; n += T) {
-                float2 v = make_float2(0.f, 0.f);
-                if (n < full) v = x2[n];
-                else if (2 * n < n_in) v.x = x[2 * n];
-                A[n] = v;
-            }
-        } else {
-            for (int n = tid; n < Nh; n += T) {
-                int i0 = 2 * n;
-                A[n] = make_float2(i0 < n_in ? x[i0] : 0.f, i0 + 1 < n_in ? x[i0 + 1] : 0.f);
-            }
+    float2 v[VPT];
+    int row = blockIdx.x;
+    if (row < nrows) load_row_pairs<VPT>(in + (int64_t)row * ld_in, n_in, Nh, tid, T, pairs_ok, v);
+    for (; row < nrows; row += gridDim.x) {
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int n = tid + i * T;
+            if (n < Nh) A[n] = v[i];
         }
-        __syncthreads();
+        // prefetch the next row of this workgroup while this one is transformed
+        if (row + (int)gridDim.x < nrows)
+            load_row_pairs<VPT>(in + (int64_t)(row + gridDim.x) * ld_in, n_in, Nh, tid, T, pairs_ok, v);
+        lds_barrier();
         fft_lds<VPT, 1>(A, plan, tid, T, tw, false);
         // split step: X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2
         float2* y = out + (int64_t)row * ld_out;
@@ -103,8 +123,20 @@ __global__ __launch_bounds__(kRowThreads) void k_r2c_rows(const float* __restric
     }
 }
 
+// Bins k = tid + i*T (k <= Nh/2) and Nh - k of one spectrum row into registers.
 template <int VPT>
-__global__ __launch_bounds__(kRowThreads) void k_c2r_rows(const float2* __restrict__ in,
+__device__ __forceinline__ void load_spec_pairs(const float2* __restrict__ X, int Nh, int tid, int T,
+                                                float2 (&a)[VPT], float2 (&b)[VPT]) {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        int k = min(tid + i * T, Nh / 2);
+        a[i] = X[k];
+        b[i] = X[Nh - k];
+    }
+}
+
+template <int VPT, int NT>
+__global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                                                           int64_t ld_in, int nrows, FftPlan plan,
                                                           float* __restrict__ out, int64_t ld_out,
                                                           int n_out, float scale, int pairs_ok) {
@@ -114,23 +146,33 @@ __global__ __launch_bounds__(kRowThreads) void k_c2r_rows(const float2* __restri
     float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
     const TwHalf tw{h, Nh};
-    for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
-        const float2* X = in + (int64_t)row * ld_in;
-        __syncthreads();
+    // the pre-step touches Nh/2 + 1 bin pairs: VPT/2 (rounded up) per thread
+    constexpr int VH = (VPT + 1) / 2 + 1;
+    float2 xa[VH], xb[VH];
+    int row = blockIdx.x;
+    if (row < nrows) load_spec_pairs<VH>(in + (int64_t)row * ld_in, Nh, tid, T, xa, xb);
+    for (; row < nrows; row += gridDim.x) {
+        lds_barrier();
         // pre-step: Z[k] = (X[k] + X*[Nh-k]) + i (X[k] - X*[Nh-k]) exp(+2 pi i k/Tf),
         // the imaginary parts of the DC and Nyquist bins are dropped
-        for (int k = tid; k <= Nh / 2; k += T) {
-            float2 xk = X[k], xm = X[Nh - k];
-            if (k == 0) { xk.y = 0.f; xm.y = 0.f; }
-            float2 w = h[k];
-            float2 a1 = make_float2(xk.x + xm.x, xk.y - xm.y);
-            float2 b1 = cmulc(make_float2(xk.x - xm.x, xk.y + xm.y), w);   // * exp(+2 pi i k/Tf)
-            float2 a2 = make_float2(xm.x + xk.x, xm.y - xk.y);
-            float2 b2 = cmul(make_float2(xm.x - xk.x, xm.y + xk.y), make_float2(-w.x, -w.y));
-            A[k] = make_float2(a1.x - b1.y, a1.y + b1.x);
-            if (k > 0) A[Nh - k] = make_float2(a2.x - b2.y, a2.y + b2.x);
+#pragma unroll
+        for (int i = 0; i < VH; ++i) {
+            int k = tid + i * T;
+            if (k <= Nh / 2) {
+                float2 xk = xa[i], xm = xb[i];
+                if (k == 0) { xk.y = 0.f; xm.y = 0.f; }
+                float2 w = h[k];
+                float2 a1 = make_float2(xk.x + xm.x, xk.y - xm.y);
+                float2 b1 = cmulc(make_float2(xk.x - xm.x, xk.y + xm.y), w);   // * exp(+2 pi i k/Tf)
+                float2 a2 = make_float2(xm.x + xk.x, xm.y - xk.y);
+                float2 b2 = cmul(make_float2(xm.x - xk.x, xm.y + xk.y), make_float2(-w.x, -w.y));
+                A[k] = make_float2(a1.x - b1.y, a1.y + b1.x);
+                if (k > 0) A[Nh - k] = make_float2(a2.x - b2.y, a2.y + b2.x);
+            }
         }
-        __syncthreads();
+        if (row + (int)gridDim.x < nrows)
+            load_spec_pairs<VH>(in + (int64_t)(row + gridDim.x) * ld_in, Nh, tid, T, xa, xb);
+        lds_barrier();
         fft_lds<VPT, 1>(A, plan, tid, T, tw, true);
         float* y = out + (int64_t)row * ld_out;
         if (pairs_ok) {
@@ -163,6 +205,8 @@ static int row_grid(int nrows) {
     return nrows < g ? nrows : g;
 }
 
+// Row kernels: 256 threads for half-lengths up to 1024, 512 above, so that
+// a thread holds at most 8 (16 above 4096) values of a row.
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
                            float2* out, int64_t ld_out, hipStream_t s) {
     FftPlan plan;
@@ -170,19 +214,18 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
     if (nrows <= 0) return hipSuccess;
     const int Nh = plan.n;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
-    const int pairs_ok = ((ld_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0) ? 1 : 0;
-    const int vpt = (Nh + kRowThreads - 1) / kRowThreads;
-    dim3 grid(row_grid(nrows)), block(kRowThreads);
-#define LAR_R2C(V)                                                                           \
-    {                                                                                        \
-        set_lds(k_r2c_rows<V>, lds);                                                         \
-        hipLaunchKernelGGL(k_r2c_rows<V>, grid, block, lds, s, in, ld_in, n_in, nrows, plan, \
-                           out, ld_out, pairs_ok);                                           \
+    const int pairs_ok =
+        ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0) ? 1 : 0;
+    dim3 grid(row_grid(nrows));
+#define LAR_R2C(V, T)                                                                           \
+    {                                                                                           \
+        set_lds(k_r2c_rows<V, T>, lds);                                                         \
+        hipLaunchKernelGGL((k_r2c_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, n_in, nrows,   \
+                           plan, out, ld_out, pairs_ok);                                        \
     }
-    if (vpt <= 4) LAR_R2C(4)
-    else if (vpt <= 8) LAR_R2C(8)
-    else if (vpt <= 16) LAR_R2C(16)
-    else if (vpt <= 32) LAR_R2C(32)
+    if (Nh <= 1024) LAR_R2C(4, 256)
+    else if (Nh <= 4096) LAR_R2C(8, 512)
+    else if (Nh <= 8192) LAR_R2C(16, 512)
     else return hipErrorInvalidValue;
 #undef LAR_R2C
     return hipGetLastError();
@@ -195,19 +238,18 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
     if (nrows <= 0) return hipSuccess;
     const int Nh = plan.n;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
-    const int pairs_ok = ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0) ? 1 : 0;
-    const int vpt = (Nh + kRowThreads - 1) / kRowThreads;
-    dim3 grid(row_grid(nrows)), block(kRowThreads);
-#define LAR_C2R(V)                                                                          \
-    {                                                                                       \
-        set_lds(k_c2r_rows<V>, lds);                                                        \
-        hipLaunchKernelGGL(k_c2r_rows<V>, grid, block, lds, s, in, ld_in, nrows, plan, out, \
-                           ld_out, n_out, scale, pairs_ok);                                 \
+    const int pairs_ok =
+        ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0) ? 1 : 0;
+    dim3 grid(row_grid(nrows));
+#define LAR_C2R(V, T)                                                                          \
+    {                                                                                          \
+        set_lds(k_c2r_rows<V, T>, lds);                                                        \
+        hipLaunchKernelGGL((k_c2r_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, nrows, plan,  \
+                           out, ld_out, n_out, scale, pairs_ok);                               \
     }
-    if (vpt <= 4) LAR_C2R(4)
-    else if (vpt <= 8) LAR_C2R(8)
-    else if (vpt <= 16) LAR_C2R(16)
-    else if (vpt <= 32) LAR_C2R(32)
+    if (Nh <= 1024) LAR_C2R(4, 256)
+    else if (Nh <= 4096) LAR_C2R(8, 512)
+    else if (Nh <= 8192) LAR_C2R(16, 512)
     else return hipErrorInvalidValue;
 #undef LAR_C2R
     return hipGetLastError();
@@ -215,7 +257,6 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
 
 // ---------------------------------------------------------------- wire pass
 
-static constexpr int kWireThreads = 256;
 
 __device__ __forceinline__ void fill_full_table(float2* t, int n, int tid, int T) {
     for (int i = tid; i < n; i += T) {
@@ -226,8 +267,8 @@ __device__ __forceinline__ void fill_full_table(float2* t, int n, int tid, int T
 }
 
 // One workgroup per tile of C consecutive time-frequency columns.
-template <int VPT, int C>
-__global__ __launch_bounds__(kWireThreads) void k_wire_fused(
+template <int VPT, int C, int NT>
+__global__ __launch_bounds__(NT) void k_wire_fused(
     const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
     const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM) {
     extern __shared__ float2 lds[];
@@ -242,42 +283,56 @@ __global__ __launch_bounds__(kWireThreads) void k_wire_fused(
 #pragma unroll
     for (int i = 0; i < VPT; ++i) acc[i] = make_float2(0.f, 0.f);
 
-    for (int k = 0; k < n_imp; ++k) {
-        __syncthreads();
+    // element e = tid + i*T of the tile is (wire p = e / C, column c = e % C);
+    // every gather below is unconditional (clamped address, value masked)
+    // so that a thread's VPT loads are all in flight together
+    float2 v[VPT];
+    auto gather_s = [&](int k) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
-            if (e < nel) {
-                int p = e / C, c = e % C, f = f0 + c;
-                float2 v = make_float2(0.f, 0.f);
-                if (p < n_wires && f < F) v = S[(int64_t)(p * n_imp + k) * ldS + f];
-                A[e] = v;
-            }
+            int p = e / C, f = f0 + e % C;
+            bool ok = e < nel && p < n_wires && f < F;
+            float2 x = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + min(f, F - 1)];
+            v[i] = ok ? x : make_float2(0.f, 0.f);
         }
-        __syncthreads();
+    };
+    gather_s(0);
+    for (int k = 0; k < n_imp; ++k) {
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int e = tid + i * T;
+            if (e < nel) A[e] = v[i];
+        }
+        lds_barrier();
         fft_lds<VPT, C>(A, plan, tid, T, twf, false);
         const float2* Rk = R + (int64_t)k * Wf * F;
+        float2 r[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int e = tid + i * T;
+            int p = min(e / C, Wf - 1), f = min(f0 + e % C, F - 1);
+            r[i] = Rk[(int64_t)p * F + f];
+        }
+        if (k + 1 < n_imp) gather_s(k + 1);    // next offset's rows, in flight during the MAC
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
             if (e < nel) {
-                int p = e / C, c = e % C, f = f0 + c;
-                if (f < F) {
-                    float2 r = Rk[(int64_t)p * F + f];
-                    float2 a = A[e];
-                    acc[i].x += a.x * r.x - a.y * r.y;
-                    acc[i].y += a.x * r.y + a.y * r.x;
-                }
+                float2 a = A[e];
+                acc[i].x += a.x * r[i].x - a.y * r[i].y;
+                acc[i].y += a.x * r[i].y + a.y * r[i].x;
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         int e = tid + i * T;
         if (e < nel) A[e] = acc[i];
     }
-    __syncthreads();
+    lds_barrier();
     fft_lds<VPT, C>(A, plan, tid, T, twf, true);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
@@ -289,33 +344,30 @@ __global__ __launch_bounds__(kWireThreads) void k_wire_fused(
     }
 }
 
-template <int VPT, int C>
+template <int VPT, int C, int NT>
 static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                               const FftPlan& plan, const float2* R, float2* M, int64_t ldM,
                               hipStream_t s) {
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
-    set_lds(k_wire_fused<VPT, C>, lds);
-    dim3 grid((F + C - 1) / C), block(kWireThreads);
-    hipLaunchKernelGGL((k_wire_fused<VPT, C>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
+    set_lds(k_wire_fused<VPT, C, NT>, lds);
+    dim3 grid((F + C - 1) / C), block(NT);
+    hipLaunchKernelGGL((k_wire_fused<VPT, C, NT>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
                        plan, R, M, ldM);
     return hipGetLastError();
 }
 
+// Tiles of 8 time-frequency columns (64-byte row segments; neighbouring
+// tiles run on one XCD and share its L2 lines) by 512 threads, so that a
+// thread holds at most 8 (16 for Wf > 512) values per tile array.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
                              int F, const float2* R, float2* M, int64_t ldM, hipStream_t s) {
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     if (F <= 0) return hipSuccess;
-    // C columns per tile: 16 (128-byte row segments) while the tile fits in
-    // 32 values per thread, else 8
-    if (nw_fft * 16 <= 8 * kWireThreads)
-        return wire_launch<8, 16>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft * 16 <= 16 * kWireThreads)
-        return wire_launch<16, 16>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft * 16 <= 32 * kWireThreads)
-        return wire_launch<32, 16>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft * 8 <= 32 * kWireThreads)
-        return wire_launch<32, 8>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
+    if (nw_fft <= 128) return wire_launch<2, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
+    if (nw_fft <= 256) return wire_launch<4, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
+    if (nw_fft <= 512) return wire_launch<8, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
+    if (nw_fft <= 1024) return wire_launch<16, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
     return hipErrorInvalidValue;
 }
 
@@ -325,7 +377,7 @@ hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_im
 // half_w); resp[k][p][f] = sum over rows with dw mod Wf = p, then a forward
 // FFT over p.
 template <int VPT, int C>
-__global__ __launch_bounds__(kWireThreads) void k_wire_spectrum(
+__global__ __launch_bounds__(256) void k_wire_spectrum(
     const float2* __restrict__ rows, int64_t ld_rows, int nrw, int half_w, int F, FftPlan plan,
     float2* __restrict__ resp) {
     extern __shared__ float2 lds[];
@@ -364,12 +416,12 @@ hipError_t launch_wire_spectrum(const float2* rows, int64_t ld_rows, int n_imp, 
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     constexpr int C = 8;
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
-    dim3 grid((F + C - 1) / C, n_imp), block(kWireThreads);
-    if (nw_fft * C <= 8 * kWireThreads) {
+    dim3 grid((F + C - 1) / C, n_imp), block(256);
+    if (nw_fft * C <= 8 * 256) {
         set_lds(k_wire_spectrum<8, C>, lds);
         hipLaunchKernelGGL((k_wire_spectrum<8, C>), grid, block, lds, s, rows, ld_rows, nrw,
                            half_w, F, plan, resp);
-    } else if (nw_fft * C <= 32 * kWireThreads) {
+    } else if (nw_fft * C <= 32 * 256) {
         set_lds(k_wire_spectrum<32, C>, lds);
         hipLaunchKernelGGL((k_wire_spectrum<32, C>), grid, block, lds, s, rows, ld_rows, nrw,
                            half_w, F, plan, resp);

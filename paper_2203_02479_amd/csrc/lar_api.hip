@@ -99,15 +99,32 @@ int lar_set_stage_events(void* const* events, int32_t n_events) {
     return LAR_OK;
 }
 
-int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, const lar_fluct* fluct,
-               float* grid, void* stream) {
+static size_t raster_bytes_min(int64_t n, const lar_fluct* f) {
+    if (!f || f->mode == 0 || n <= 0) return 0;
+    return raster_ws_fixed(n);
+}
+
+// recommended: room for 16 deferred bins per depo (a few per depo are
+// typical) plus a margin
+static size_t raster_bytes(int64_t n, const lar_fluct* f) {
+    size_t fixed = raster_bytes_min(n, f);
+    if (!fixed) return 0;
+    return fixed + ((size_t)n * 16 + 4096) * kDeferredBytes;
+}
+
+int lar_raster_workspace(const lar_plane* plane, int64_t n_depos, const lar_fluct* fluct,
+                         size_t* bytes) {
     int st;
     if ((st = check_plane(plane))) return st;
-    if ((st = check_depos(depos))) return st;
     if ((st = check_fluct(fluct))) return st;
-    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
-    if (depos->n == 0) return LAR_OK;
-    if (!grid) return LAR_EINVAL;
+    if (n_depos < 0 || !bytes) return LAR_EINVAL;
+    *bytes = raster_bytes(n_depos, fluct);
+    return LAR_OK;
+}
+
+static int raster_impl(const lar_plane* plane, const lar_depos* depos, float nsigma,
+                       const lar_fluct* fluct, float* grid, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
     RasterArgs a;
     a.n_ticks = plane->n_ticks;
     a.n_rows = plane->n_wires * plane->n_imp;
@@ -122,9 +139,23 @@ int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, con
     a.plane = fluct ? fluct->plane : 0u;
     a.seed = fluct ? fluct->seed : 0ull;
     LAR_TRY(launch_raster(a, depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x,
-                          depos->n, grid, (hipStream_t)stream));
-    LAR_TRY(stage_mark(1, (hipStream_t)stream));
+                          depos->n, grid, ws, ws_bytes, stream));
+    LAR_TRY(stage_mark(1, stream));
     return LAR_OK;
+}
+
+int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, const lar_fluct* fluct,
+               float* grid, void* ws, size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_plane(plane))) return st;
+    if ((st = check_depos(depos))) return st;
+    if ((st = check_fluct(fluct))) return st;
+    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    if (depos->n == 0) return LAR_OK;
+    if (!grid) return LAR_EINVAL;
+    const size_t need = raster_bytes_min(depos->n, fluct);
+    if (need && (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256)) return LAR_EWORKSPACE;
+    return raster_impl(plane, depos, nsigma, fluct, grid, ws, ws_bytes, (hipStream_t)stream);
 }
 
 // fftconv workspace: [spectrum of grid rows: R_rows x ld][wire-pass output: N_w x ld]
@@ -177,11 +208,14 @@ static size_t grid_bytes(const lar_plane* p) {
     return align_up((size_t)p->n_wires * p->n_imp * p->n_ticks * sizeof(float), 256);
 }
 
-int lar_sim_plane_workspace(const lar_plane* plane, size_t* bytes) {
+// sim_plane workspace: [grid: R_rows x n_ticks floats][fftconv workspace][raster workspace]
+int lar_sim_plane_workspace(const lar_plane* plane, int64_t n_depos, const lar_fluct* fluct,
+                            size_t* bytes) {
     int st;
     if ((st = check_fft(plane))) return st;
-    if (!bytes) return LAR_EINVAL;
-    *bytes = grid_bytes(plane) + fftconv_bytes(plane);
+    if ((st = check_fluct(fluct))) return st;
+    if (n_depos < 0 || !bytes) return LAR_EINVAL;
+    *bytes = grid_bytes(plane) + fftconv_bytes(plane) + raster_bytes(n_depos, fluct);
     return LAR_OK;
 }
 
@@ -194,14 +228,21 @@ int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
     if ((st = check_fluct(fluct))) return st;
     if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
     if (!resp || !wave) return LAR_EINVAL;
-    size_t need = grid_bytes(plane) + fftconv_bytes(plane);
+    const size_t head = grid_bytes(plane) + fftconv_bytes(plane);
+    const size_t need = head + raster_bytes_min(depos->n, fluct);
     if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    float* grid = reinterpret_cast<float*>(ws);
+    char* w = reinterpret_cast<char*>(ws);
+    float* grid = reinterpret_cast<float*>(w);
     LAR_TRY(launch_fill(grid, (int64_t)plane->n_wires * plane->n_imp * plane->n_ticks, s));
     LAR_TRY(stage_mark(0, s));
-    if ((st = lar_raster(plane, depos, nsigma, fluct, grid, stream))) return st;
-    return fftconv_impl(plane, grid, resp, wave, reinterpret_cast<char*>(ws) + grid_bytes(plane), s);
+    if (depos->n > 0) {
+        if ((st = raster_impl(plane, depos, nsigma, fluct, grid, w + head, ws_bytes - head, s)))
+            return st;
+    } else {
+        LAR_TRY(stage_mark(1, s));
+    }
+    return fftconv_impl(plane, grid, resp, wave, w + grid_bytes(plane), s);
 }
 
 // response spectrum workspace: time spectra of the n_imp*(2H+1) response rows

@@ -37,6 +37,15 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
+// Workgroup barrier that orders LDS only: outstanding global loads and
+// atomics are not waited for (a plain __syncthreads also fences global
+// memory, which stalls on in-flight prefetches and fire-and-forget atomics).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Small DFTs, sign -1 (forward) or +1 (inverse) in the exponent.
 template <int R>
 __device__ __forceinline__ void dft_small(float2* v, bool inv);
@@ -120,7 +129,7 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
             dst[b] = ((j - k) * R + k) * NS + s;
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         if (dst[b] >= 0) {
@@ -129,7 +138,7 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
             for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * NS] = v[b][r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // Full transform of NS interleaved length-n sequences in LDS by T threads,
@@ -179,8 +188,15 @@ struct RasterArgs {
     uint32_t event, plane;
     uint64_t seed;
 };
+// Fluctuated rasters need a workspace: raster_ws_fixed(n) bytes of header
+// and sub-chunk flags, then a queue of 16-byte deferred bins (capacity =
+// the remaining bytes / 16; any capacity, zero included, gives the same
+// result).  The mean raster needs none.
+size_t raster_ws_fixed(int64_t n);
+constexpr size_t kDeferredBytes = 16;
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
-                         const float* st, const float* sx, int64_t n, float* grid, hipStream_t s);
+                         const float* st, const float* sx, int64_t n, float* grid, void* ws,
+                         size_t ws_bytes, hipStream_t s);
 hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
                                 const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                                 hipStream_t s);

@@ -27,8 +27,8 @@ namespace lar {
 struct PhiloxStream {
     uint32_t k0, k1;
     uint32_t c0, c1, c2, c3;
-    uint32_t b2, b3;
-    int left;
+    uint32_t b0, b1, b2, b3;
+    int left;   // 0: no buffered uniform, 2: second uniform of the block left, 3: primed block
 };
 
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
@@ -39,8 +39,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         uint32_t n0 = hi1 ^ c1 ^ k0;
         uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -69,6 +71,10 @@ __device__ __forceinline__ void stream_init(PhiloxStream& s, uint64_t seed, uint
 }
 
 __device__ __forceinline__ double next_uniform(PhiloxStream& s) {
+    if (s.left == 3) {
+        s.left = 2;
+        return u52(s.b0, s.b1);
+    }
     if (s.left == 0) {
         uint32_t o0 = s.c0, o1 = s.c1, o2 = s.c2, o3 = s.c3;
         philox4x32_10(o0, o1, o2, o3, s.k0, s.k1);
@@ -80,6 +86,19 @@ __device__ __forceinline__ double next_uniform(PhiloxStream& s) {
     }
     s.left = 0;
     return u52(s.b2, s.b3);
+}
+
+// Compute the stream's first Philox block now (so that lanes about to take
+// different sampler branches run it together); draws are unchanged.
+__device__ __forceinline__ void stream_prime(PhiloxStream& s) {
+    uint32_t o0 = s.c0, o1 = s.c1, o2 = s.c2, o3 = s.c3;
+    philox4x32_10(o0, o1, o2, o3, s.k0, s.k1);
+    s.c3 += 1u;
+    s.b0 = o0;
+    s.b1 = o1;
+    s.b2 = o2;
+    s.b3 = o3;
+    s.left = 3;   // marks a primed block: both uniforms still unread
 }
 
 // ---------------------------------------------------------------- samplers
@@ -96,15 +115,36 @@ __device__ double stirling_tail(double k) {
     return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0) * r2) * r2) * r;
 }
 
-// Binomial by inversion from k = 0 (p <= 1/2, n p < 10).
+// x^n for a non-negative integer n (held in a double): square-and-multiply
+// over the bits of n from the least significant, IEEE multiplies only.
+__device__ __forceinline__ double ipow_n(double x, double n) {
+#pragma clang fp contract(off)
+    uint64_t e = (uint64_t)n;
+    double r = 1.0, b = x;
+    while (e) {
+        if (e & 1u) r = r * b;
+        e >>= 1;
+        if (e) b = b * b;
+    }
+    return r;
+}
+
+// Binomial by inversion from k = 0 (p <= 1/2, n p < 10): f(0) = (1-p)^n,
+// f(k) = f(k-1) ((n+1) r / k - r), r = p/(1-p).  When n p < 1 the first
+// uniform is compared with a lower bound of f(0) first: (1-p)^n >= 1 - n p
+// (Bernoulli), minus a margin above the rounding of q and of the powering,
+// so the early return of 0 happens only where the full test returns 0.
 __device__ double binom_inversion(double n, double p, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double q = 1.0 - p;
     double ratio = p / q;
     double g = ratio * (n + 1.0);
-    double f0 = exp(n * log1p(-p));
+    double u = next_uniform(s);
+    double np = n * p;
+    if (np < 1.0 && u < (1.0 - np) - (n + 64.0) * 8.8817841970012523e-16) return 0.0;
+    double f0 = ipow_n(q, n);
     for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
-        double u = next_uniform(s);
+        if (tries > 0) u = next_uniform(s);
         double f = f0;
         double k = 0.0;
         for (;;) {
@@ -121,23 +161,30 @@ __device__ double binom_inversion(double n, double p, PhiloxStream& s) {
 // Binomial by BTRD, transformed rejection with decomposition (p <= 1/2, n p >= 10).
 __device__ double binom_btrd(double n, double p, PhiloxStream& s) {
 #pragma clang fp contract(off)
-    double m = floor((n + 1.0) * p);
-    double r = p / (1.0 - p);
-    double nr = (n + 1.0) * r;
+    // constants of the fast acceptance region first; those of the slow
+    // path are formed only when it is reached (identical values)
     double npq = n * p * (1.0 - p);
     double spq = sqrt(npq);
     double b = 1.15 + 2.53 * spq;
     double a = -0.0873 + 0.0248 * b + 0.01 * p;
     double c = n * p + 0.5;
-    double alpha = (2.83 + 5.1 / b) * spq;
     double vr = 0.92 - 4.2 / b;
     double urvr = 0.86 * vr;
+    double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
+    bool slow_ready = false;
     for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
         double v = next_uniform(s);
         double u;
         if (v <= urvr) {
             u = v / vr - 0.43;
             return floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+        }
+        if (!slow_ready) {
+            m = floor((n + 1.0) * p);
+            r = p / (1.0 - p);
+            nr = (n + 1.0) * r;
+            alpha = (2.83 + 5.1 / b) * spq;
+            slow_ready = true;
         }
         if (v >= vr) {
             u = next_uniform(s) - 0.5;
@@ -173,37 +220,35 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s) {
                       - stirling_tail(k) - stirling_tail(n - k))
             return k;
     }
+    if (!slow_ready) m = floor((n + 1.0) * p);
     return m;
 }
 
-__device__ double sample_binomial(double n, double p, PhiloxStream& s) {
+// Poisson by inversion (0 < lam < 10).  For lam < 1 the first uniform is
+// compared with exp(-lam) >= 1 - lam (minus a margin above exp's rounding)
+// first, which decides k = 0 exactly where the full test does.
+__device__ double poisson_inversion(double lam, PhiloxStream& s) {
 #pragma clang fp contract(off)
-    if (!(n > 0.0) || !(p > 0.0)) return 0.0;
-    if (p >= 1.0) return n;
-    bool flip = p > 0.5;
-    double pp = flip ? 1.0 - p : p;
-    double k = (n * pp < 10.0) ? binom_inversion(n, pp, s) : binom_btrd(n, pp, s);
-    return flip ? n - k : k;
+    double u = next_uniform(s);
+    if (lam < 1.0 && u < (1.0 - lam) - 1e-13) return 0.0;
+    double p0 = exp(-lam);
+    for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
+        if (tries > 0) u = next_uniform(s);
+        double p = p0, cdf = p0, k = 0.0;
+        while (u > cdf) {
+            if (k > 200.0) break;
+            k = k + 1.0;
+            p = p * lam / k;
+            cdf = cdf + p;
+        }
+        if (u <= cdf) return k;
+    }
+    return floor(lam);
 }
 
-__device__ double sample_poisson(double lam, PhiloxStream& s) {
+// Poisson by PTRS, transformed rejection with squeeze (lam >= 10).
+__device__ double poisson_ptrs(double lam, PhiloxStream& s) {
 #pragma clang fp contract(off)
-    if (!(lam > 0.0)) return 0.0;
-    if (lam < 10.0) {
-        double p0 = exp(-lam);
-        for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
-            double u = next_uniform(s);
-            double p = p0, cdf = p0, k = 0.0;
-            while (u > cdf) {
-                if (k > 200.0) break;
-                k = k + 1.0;
-                p = p * lam / k;
-                cdf = cdf + p;
-            }
-            if (u <= cdf) return k;
-        }
-        return floor(lam);
-    }
     double slam = sqrt(lam);
     double loglam = log(lam);
     double b = 0.931 + 2.53 * slam;
@@ -223,16 +268,132 @@ __device__ double sample_poisson(double lam, PhiloxStream& s) {
     return floor(lam);
 }
 
-// Signed count of one bin.
-__device__ __noinline__ float bin_count(int mode, float q, double p, uint64_t seed, uint32_t depo,
-                                        uint32_t event, uint32_t bin, uint32_t plane) {
+// First try of BTRD restricted to its fast acceptance region (the same
+// operations as the full sampler's first try): the count, or -1 when the
+// full sampler has to run.
+__device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s) {
+#pragma clang fp contract(off)
+    double npq = n * p * (1.0 - p);
+    double spq = sqrt(npq);
+    double b = 1.15 + 2.53 * spq;
+    double a = -0.0873 + 0.0248 * b + 0.01 * p;
+    double c = n * p + 0.5;
+    double vr = 0.92 - 4.2 / b;
+    double urvr = 0.86 * vr;
+    double v = next_uniform(s);
+    if (v <= urvr) {
+        double u = v / vr - 0.43;
+        return floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+    }
+    return -1.0;
+}
+
+// First try of PTRS restricted to its immediate acceptance (us >= 0.07 and
+// v <= v_r): the count, or -1 when the full sampler has to run.
+__device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s) {
+#pragma clang fp contract(off)
+    double slam = sqrt(lam);
+    double b = 0.931 + 2.53 * slam;
+    double a = -0.059 + 0.02483 * b;
+    double vr = 0.9277 - 3.6224 / (b - 2.0);
+    double u = next_uniform(s) - 0.5;
+    double v = next_uniform(s);
+    double us = 0.5 - fabs(u);
+    double k = floor((2.0 * a / us + b) * u + lam + 0.43);
+    if (us >= 0.07 && v <= vr) return k;
+    return -1.0;
+}
+
+// Signed count of one bin drawn with inversion or the rejection samplers'
+// fast region only; returns NaN when the bin needs the full rejection
+// sampler (bin_count_in<true>, which redraws it from the same counter).
+template <int MODE>
+__device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
+                                                uint32_t event, uint32_t bin, uint32_t plane) {
+#pragma clang fp contract(off)
+    PhiloxStream s;
+    stream_init(s, seed, depo, event, bin, plane);
+    stream_prime(s);
+    double aq = fabs((double)q);
+    double r;
+    if (MODE == 1) {
+        double n = rint(aq);
+        if (!(n > 0.0) || !(p > 0.0)) {
+            r = 0.0;
+        } else if (p >= 1.0) {
+            r = n;
+        } else {
+            bool flip = p > 0.5;
+            double pp = flip ? 1.0 - p : p;
+            double k = (n * pp < 10.0) ? binom_inversion(n, pp, s) : binom_btrd_fast(n, pp, s);
+            if (k < 0.0) return __builtin_nanf("");
+            r = flip ? n - k : k;
+        }
+    } else {
+        double lam = aq * p;
+        if (!(lam > 0.0)) {
+            r = 0.0;
+        } else {
+            r = (lam < 10.0) ? poisson_inversion(lam, s) : poisson_ptrs_fast(lam, s);
+            if (r < 0.0) return __builtin_nanf("");
+        }
+    }
+    float f = (float)r;
+    return q < 0.f ? -f : f;
+}
+
+// Whether a bin's draw takes the rejection samplers (BTRD / PTRS) rather
+// than inversion or a trivial case: mode 1 with n min(p,1-p) >= 10, mode 2
+// with lambda >= 10.
+__device__ __forceinline__ bool rejection_regime(int mode, float q, double p) {
+#pragma clang fp contract(off)
+    double aq = fabs((double)q);
+    if (mode == 1) {
+        double n = rint(aq);
+        if (!(n > 0.0) || !(p > 0.0) || p >= 1.0) return false;
+        double pp = p > 0.5 ? 1.0 - p : p;
+        return !(n * pp < 10.0);
+    }
+    double lam = aq * p;
+    return lam > 0.0 && !(lam < 10.0);
+}
+
+// Signed count of one bin, for a bin known to be in the given regime.
+template <bool REJECT>
+__device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint64_t seed,
+                                              uint32_t depo, uint32_t event, uint32_t bin,
+                                              uint32_t plane) {
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
     double aq = fabs((double)q);
-    double n = (mode == 1) ? sample_binomial(rint(aq), p, s) : sample_poisson(aq * p, s);
-    float r = (float)n;
-    return q < 0.f ? -r : r;
+    double r;
+    if (mode == 1) {
+        double n = rint(aq);
+        if (!(n > 0.0) || !(p > 0.0)) {
+            r = 0.0;
+        } else if (p >= 1.0) {
+            r = n;
+        } else {
+            bool flip = p > 0.5;
+            double pp = flip ? 1.0 - p : p;
+            double k = REJECT ? binom_btrd(n, pp, s) : binom_inversion(n, pp, s);
+            r = flip ? n - k : k;
+        }
+    } else {
+        double lam = aq * p;
+        r = !(lam > 0.0) ? 0.0 : (REJECT ? poisson_ptrs(lam, s) : poisson_inversion(lam, s));
+    }
+    float f = (float)r;
+    return q < 0.f ? -f : f;
+}
+
+// Signed count of one bin: sign(q) * Binomial(rint|q|, p) or Poisson(|q| p).
+__device__ __forceinline__ float bin_count(int mode, float q, double p, uint64_t seed, uint32_t depo,
+                                           uint32_t event, uint32_t bin, uint32_t plane) {
+    return rejection_regime(mode, q, p)
+               ? bin_count_in<true>(mode, q, p, seed, depo, event, bin, plane)
+               : bin_count_in<false>(mode, q, p, seed, depo, event, bin, plane);
 }
 
 __global__ void k_sample_counts(int mode, int64_t n, const float* __restrict__ q,
@@ -287,11 +448,13 @@ __device__ __forceinline__ Window axis_window(double mu, double sg, double ns, d
 
 // Tail mass of the standard normal beyond |z|.
 __device__ __forceinline__ float normal_tail(float z) {
+#pragma clang fp contract(off)
     return 0.5f * erfcf(fabsf(z) * 0.70710678118654752f);
 }
 
 // Edge e's standardized coordinate (FP64 subtraction, then FP32).
 __device__ __forceinline__ float edge_z(double org, double wd, int e, double mu, double inv_sg) {
+#pragma clang fp contract(off)
     return (float)((org + (double)e * wd - mu) * inv_sg);
 }
 
@@ -332,60 +495,110 @@ __device__ __forceinline__ float single_weight(double mu, double sg, double org,
 }
 
 // ---------------------------------------------------------------- raster kernel
+//
+// Every wave works alone on sub-chunks of kSub consecutive depos: windows,
+// weights into its LDS slots, patches summed into its private LDS tile over
+// the sub-chunk's bounding box, then one global float atomic per non-zero
+// tile cell.  A wave instruction never has two lanes on the same tile cell
+// (the mean path covers one depo per instruction; the fluctuated path adds
+// the lanes of one depo at a time), so the tile is accumulated with plain
+// LDS read-add-write: float atomics in LDS are slower than in L2 on this
+// chip.  Sub-chunks whose box exceeds the tile go straight to global atomics.
+//
+// Fluctuation runs in three kernels so that the hot one stays small in
+// registers: k_raster draws every bin by inversion or in the rejection
+// samplers' fast region and queues the rest in the workspace;
+// k_raster_deferred redraws the queued bins with the full samplers;
+// k_raster_overflow redraws all deferred bins of sub-chunks whose queue
+// reservation did not fit.  A bin's count depends only on its counter, so
+// which kernel draws it does not change the result.
 
 static constexpr int kRasterThreads = 256;
-static constexpr int kChunk = 128;        // depos per chunk
-static constexpr int kMaxT = 16;          // regular window limits (bins)
+static constexpr int kWaves = kRasterThreads / 64;
+static constexpr int kSub = 16;           // depos per wave sub-chunk
+static constexpr int kMaxT = 16;          // window limits of the LDS slots (bins)
 static constexpr int kMaxX = 32;
-static constexpr int kSlot = kMaxT + kMaxX + 1;   // +1 pad against LDS bank conflicts
-static constexpr int kTileCap = 8192;     // LDS tile (floats)
+static constexpr int kSlot = kMaxT + kMaxX + 1;
+static constexpr int kWaveTile = 1024;    // floats of a wave's private tile
+static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
+static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+
+// Deferred bin: depo index, impact row, tick, bin probability (float).
+struct DeferredBin {
+    uint32_t depo, m, j;
+    float p;
+};
+
+// Workspace of a fluctuated raster: header, one flag byte per sub-chunk,
+// then the queue.  The queue capacity is whatever the workspace holds.
+struct RasterWs {
+    unsigned long long count;    // bins queued (may exceed the capacity)
+};
+
+size_t raster_ws_fixed(int64_t n) {
+    const int64_t nsub = (n + kSub - 1) / kSub;
+    return 256 + (((size_t)nsub + 255) / 256) * 256;
+}
 
 __device__ __forceinline__ bool depo_finite(float a, float b, float c, float d, float e) {
     return isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) && isfinite(e);
 }
 
-template <bool FLUCT>
-__device__ __forceinline__ float cell_value(const RasterArgs& A, float q, float wt, float wx,
-                                            uint32_t depo, int m, int j) {
-    if (!FLUCT) return q * wt * wx;
-    double p = (double)(wt * wx);
-    uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-    return bin_count(A.mode, q, p, A.seed, depo, A.event, bin, A.plane);
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
-template <bool FLUCT>
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <int MODE>
 __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const float* __restrict__ Q,
                                                            const float* __restrict__ Tm,
                                                            const float* __restrict__ X,
                                                            const float* __restrict__ ST,
                                                            const float* __restrict__ SX, int64_t n,
-                                                           float* __restrict__ grid) {
-    __shared__ float s_w[kChunk * kSlot];
-    __shared__ float s_tile[kTileCap];
-    __shared__ int s_jlo[kChunk], s_nt[kChunk], s_mlo[kChunk], s_nx[kChunk];
-    __shared__ float s_q[kChunk];
-    __shared__ int s_off[kChunk + 1];
-    __shared__ int s_big[kChunk];
-    __shared__ int s_nbig;
-    __shared__ int s_box[4];   // jmin, jmax, mmin, mmax
-    __shared__ int s_wsum[kRasterThreads / 64];
+                                                           float* __restrict__ grid,
+                                                           RasterWs* __restrict__ ws,
+                                                           uint8_t* __restrict__ flags,
+                                                           DeferredBin* __restrict__ queue,
+                                                           unsigned long long cap) {
+    constexpr bool FLUCT = MODE != 0;
+    __shared__ float s_w[kWaves][kSub * kSlot];
+    __shared__ float s_tile[kWaves][kWaveTile];
+    __shared__ int s_meta[kWaves][4][kSub];            // jlo, nt, mlo, nx (nt<0 / nx<0: point axis)
+    __shared__ float s_q[kWaves][kSub];
+    __shared__ int s_off[kWaves][FLUCT ? kSub + 1 : 1];
+    __shared__ uint16_t s_queue[kWaves][FLUCT ? kWaveQueue : 1];   // (depo:4 | row:5 | tick:4)
 
-    const int tid = threadIdx.x;
-    for (int i = tid; i < kTileCap; i += kRasterThreads) s_tile[i] = 0.f;
-    const int64_t nchunks = (n + kChunk - 1) / kChunk;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float* W = s_w[wv];
+    float* tile = s_tile[wv];
+    int* jlo_ = s_meta[wv][0];
+    int* nt_ = s_meta[wv][1];
+    int* mlo_ = s_meta[wv][2];
+    int* nx_ = s_meta[wv][3];
+    float* q_ = s_q[wv];
+    for (int i = lane; i < kWaveTile; i += 64) tile[i] = 0.f;
 
-    for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-        const int64_t base = chunk * kChunk;
-        if (tid == 0) {
-            s_nbig = 0;
-            s_box[0] = INT_MAX; s_box[1] = INT_MIN; s_box[2] = INT_MAX; s_box[3] = INT_MIN;
-        }
-        __syncthreads();
-        // ---- windows (one thread per depo)
-        int cells = 0;
-        if (tid < kChunk) {
-            int64_t d = base + tid;
-            int nt = 0, nx = 0, jlo = 0, mlo = 0;
+    const int64_t nsub = (n + kSub - 1) / kSub;
+    for (int64_t sub = (int64_t)blockIdx.x * kWaves + wv; sub < nsub;
+         sub += (int64_t)gridDim.x * kWaves) {
+        const int64_t base = sub * kSub;
+        // ---- windows: lane d < kSub takes depo base + d
+        int nt = 0, nx = 0, jlo = 0, mlo = 0, cells = 0;
+        int bj0 = INT_MAX, bj1 = INT_MIN, bm0 = INT_MAX, bm1 = INT_MIN;
+        if (lane < kSub) {
+            int64_t d = base + lane;
             float q = 0.f;
             if (d < n) {
                 q = Q[d];
@@ -394,113 +607,285 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
                     Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
                     Window wx = wt.n ? axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows)
                                      : Window{0, 0, false};
-                    if (wt.n && wx.n) {
-                        nt = wt.n; nx = wx.n; jlo = wt.lo; mlo = wx.lo;
-                        if (wt.point) nt = -nt;   // sign marks a point axis (weights skip erfc)
-                        if (wx.point) nx = -nx;
+                    if (wt.n && wx.n && wt.n <= kMaxT && wx.n <= kMaxX) {
+                        nt = wt.point ? -wt.n : wt.n;
+                        nx = wx.point ? -wx.n : wx.n;
+                        jlo = wt.lo;
+                        mlo = wx.lo;
+                        cells = wt.n * wx.n;
+                        bj0 = jlo; bj1 = jlo + wt.n - 1; bm0 = mlo; bm1 = mlo + wx.n - 1;
                     }
                 }
             }
-            int ant = abs(nt), anx = abs(nx);
-            bool regular = ant > 0 && ant <= kMaxT && anx <= kMaxX;
-            if (ant > 0 && !regular) {
-                int slot = atomicAdd(&s_nbig, 1);
-                s_big[slot] = tid;
-            }
-            s_jlo[tid] = jlo; s_mlo[tid] = mlo; s_nt[tid] = nt; s_nx[tid] = nx; s_q[tid] = q;
-            cells = regular ? ant * anx : 0;
-            if (regular) {
-                atomicMin(&s_box[0], jlo); atomicMax(&s_box[1], jlo + ant - 1);
-                atomicMin(&s_box[2], mlo); atomicMax(&s_box[3], mlo + anx - 1);
-            }
+            jlo_[lane] = jlo; nt_[lane] = nt; mlo_[lane] = mlo; nx_[lane] = nx; q_[lane] = q;
         }
-        // ---- exclusive scan of cell counts (threads >= kChunk contribute 0)
-        {
-            int lane = tid & 63, wv = tid >> 6;
+        const int jmin = wave_min(bj0), jmax = wave_max(bj1);
+        const int mmin = wave_min(bm0), mmax = wave_max(bm1);
+        if (jmax < jmin) continue;   // no regular depo in this sub-chunk (uniform)
+        const int span_t = jmax - jmin + 1, span_x = mmax - mmin + 1;
+        const bool use_tile = span_t * span_x <= kWaveTile;
+        if (FLUCT) {   // exclusive prefix of cell counts over the sub-chunk
             int v = cells;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 int u = __shfl_up(v, o, 64);
                 if (lane >= o) v += u;
             }
-            if (lane == 63) s_wsum[wv] = v;
-            __syncthreads();
-            int add = 0;
-            for (int i = 0; i < wv; ++i) add += s_wsum[i];
-            if (tid < kChunk) s_off[tid] = add + v - cells;
-            if (tid == kChunk - 1) s_off[kChunk] = add + v;
+            if (lane < kSub) s_off[wv][lane] = v - cells;
+            if (lane == kSub - 1) s_off[wv][kSub] = v;
         }
-        __syncthreads();
-        // ---- 1D weights: two threads per depo (time axis, pitch axis)
+        // ---- weights: lanes 0..kSub-1 time axis, kSub..2kSub-1 pitch axis
         {
-            int d = tid >> 1, ax = tid & 1;
-            int64_t gd = base + d;
-            int nt = s_nt[d], nx = s_nx[d];
-            int ant = abs(nt), anx = abs(nx);
-            if (gd < n && ant > 0 && ant <= kMaxT && anx <= kMaxX) {
-                float* w = s_w + d * kSlot;
-                if (ax == 0) {
-                    Window win{s_jlo[d], ant, nt < 0};
+            const int d = lane & (kSub - 1);
+            const int64_t gd = base + d;
+            const int ntd = __shfl(nt, d, 64), nxd = __shfl(nx, d, 64);
+            const int jlod = __shfl(jlo, d, 64), mlod = __shfl(mlo, d, 64);
+            if (lane < 2 * kSub && ntd != 0) {
+                float* w = W + d * kSlot;
+                if (lane < kSub) {
+                    Window win{jlod, abs(ntd), ntd < 0};
                     axis_weights(Tm[gd], ST[gd], A.org_t, A.wd_t, win, w, 1);
                 } else {
-                    Window win{s_mlo[d], anx, nx < 0};
+                    Window win{mlod, abs(nxd), nxd < 0};
                     axis_weights(X[gd], SX[gd], A.org_x, A.wd_x, win, w + kMaxT, 1);
                 }
             }
         }
-        __syncthreads();
-        // ---- cells
-        const int total = s_off[kChunk];
-        const int jmin = s_box[0], mmin = s_box[2];
-        const int span_t = s_box[1] - jmin + 1, span_x = s_box[3] - mmin + 1;
-        const bool use_tile = total > 0 && (int64_t)span_t * span_x <= kTileCap;
-        {
+        wave_lds_sync();
+
+        if (!FLUCT) {
+            // ---- mean patches: one depo per instruction, lanes = rows x TW ticks
+            for (int d = 0; d < kSub; ++d) {
+                const int ntd = nt_[d];
+                if (ntd == 0) continue;
+                const int ant = abs(ntd), anx = abs(nx_[d]);
+                const int sh = ant <= 4 ? 2 : (ant <= 8 ? 3 : 4);
+                const int b = lane & ((1 << sh) - 1);
+                const int r0 = lane >> sh, step = 64 >> sh;
+                if (b < ant) {
+                    const float* w = W + d * kSlot;
+                    const float qwt = q_[d] * w[b];
+                    const int j = jlo_[d] + b, m0 = mlo_[d];
+                    if (use_tile) {
+                        float* trow = tile + (m0 - mmin) * span_t + (j - jmin);
+                        for (int a = r0; a < anx; a += step) trow[a * span_t] += qwt * w[kMaxT + a];
+                    } else {
+                        for (int a = r0; a < anx; a += step)
+                            atomicAdd(&grid[(int64_t)(m0 + a) * A.ld + j], qwt * w[kMaxT + a]);
+                    }
+                }
+                // other lanes touch these cells for the next depo: keep program order
+                asm volatile("" ::: "memory");
+            }
+        } else {
+            // ---- fluctuated patches: lanes flat over the sub-chunk's cells
+            const int total = s_off[wv][kSub];
+            int nq = 0;   // buffered deferred bins (wave-uniform)
             int d = 0;
-            for (int c = tid; c < total; c += kRasterThreads) {
-                while (s_off[d + 1] <= c) ++d;
-                int ant = abs(s_nt[d]);
-                int local = c - s_off[d];
-                int a = local / ant, b = local - a * ant;
-                const float* w = s_w + d * kSlot;
-                int j = s_jlo[d] + b, m = s_mlo[d] + a;
-                float v = cell_value<FLUCT>(A, s_q[d], w[b], w[kMaxT + a], (uint32_t)(base + d), m, j);
-                if (v != 0.f) {
-                    if (use_tile)
-                        atomicAdd(&s_tile[(m - mmin) * span_t + (j - jmin)], v);
-                    else
-                        atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+            for (int c0 = 0; c0 < total; c0 += 64) {
+                const int c = c0 + lane;
+                int m = 0, j = 0, todo = -1;
+                float v = 0.f;
+                bool defer = false;
+                int code = 0;
+                if (c < total) {
+                    while (s_off[wv][d + 1] <= c) ++d;
+                    const int ant = abs(nt_[d]);
+                    const int local = c - s_off[wv][d];
+                    const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
+                    const int b = local - a * ant;
+                    const float* w = W + d * kSlot;
+                    j = jlo_[d] + b;
+                    m = mlo_[d] + a;
+                    const double p = (double)(w[b] * w[kMaxT + a]);
+                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                    v = bin_count_fast<MODE>(q_[d], p, A.seed, (uint32_t)(base + d), A.event, bin,
+                                             A.plane);
+                    if (v != v) {
+                        defer = true;
+                        code = (d << 9) | (a << 4) | b;
+                    } else if (v != 0.f) {
+                        todo = d;
+                    }
+                }
+                const uint64_t dm = __ballot(defer);
+                if (defer) s_queue[wv][nq + __popcll(dm & ((1ull << lane) - 1))] = (uint16_t)code;
+                nq += __popcll(dm);
+                // add the drawn counts, the lanes of one depo at a time
+                for (;;) {
+                    const int first = wave_min(todo < 0 ? INT_MAX : todo);
+                    if (first == INT_MAX) break;
+                    if (todo == first) {
+                        if (use_tile)
+                            tile[(m - mmin) * span_t + (j - jmin)] += v;
+                        else
+                            atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                        todo = -1;
+                    }
+                    asm volatile("" ::: "memory");
+                }
+                // move buffered bins to the workspace queue when the next
+                // instruction could overflow the buffer, and at the end
+                if (nq > kWaveQueue - 64 || (c0 + 64 >= total && nq > 0)) {
+                    wave_lds_sync();
+                    unsigned long long gb = 0;
+                    if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
+                    gb = __shfl(gb, 0, 64);
+                    const bool fits = gb + (unsigned long long)nq <= cap;
+                    for (int e = lane; e < nq; e += 64) {
+                        const unsigned long long slot = gb + (unsigned long long)e;
+                        if (slot >= cap) continue;
+                        DeferredBin db;
+                        if (fits) {
+                            const int cd = s_queue[wv][e];
+                            const int dd = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                            const float* w = W + dd * kSlot;
+                            db.depo = (uint32_t)(base + dd);
+                            db.m = (uint32_t)(mlo_[dd] + a);
+                            db.j = (uint32_t)(jlo_[dd] + b);
+                            db.p = w[b] * w[kMaxT + a];
+                        } else {
+                            db.depo = kInvalid; db.m = 0; db.j = 0; db.p = 0.f;
+                        }
+                        queue[slot] = db;
+                    }
+                    if (!fits && lane == 0) flags[sub] = 1;
+                    nq = 0;
+                    wave_lds_sync();
                 }
             }
         }
-        __syncthreads();
-        // ---- flush the tile (one atomic per non-zero cell), leave it zeroed
+        // ---- flush: one global atomic per non-zero cell, leave the tile zeroed
         if (use_tile) {
             const int area = span_t * span_x;
-            for (int e = tid; e < area; e += kRasterThreads) {
-                float v = s_tile[e];
+            for (int e = lane; e < area; e += 64) {
+                float v = tile[e];
                 if (v != 0.f) {
-                    int r = e / span_t, cidx = e - r * span_t;
-                    atomicAdd(&grid[(int64_t)(mmin + r) * A.ld + jmin + cidx], v);
-                    s_tile[e] = 0.f;
+                    int r = e / span_t, ci = e - r * span_t;
+                    atomicAdd(&grid[(int64_t)(mmin + r) * A.ld + jmin + ci], v);
+                    tile[e] = 0.f;
                 }
             }
         }
-        // ---- depos with windows beyond the slots: all threads, per cell
-        const int nbig = s_nbig;
-        for (int bi = 0; bi < nbig; ++bi) {
-            int d = s_big[bi];
-            int64_t gd = base + d;
-            int nt = s_nt[d], nx = s_nx[d];
-            int ant = abs(nt), anx = abs(nx);
-            Window wt{s_jlo[d], ant, nt < 0}, wx{s_mlo[d], anx, nx < 0};
-            float t = Tm[gd], st = ST[gd], x = X[gd], sx = SX[gd], q = s_q[d];
-            int64_t ncell = (int64_t)ant * anx;
+    }
+}
+
+// Clears the queue counter and the sub-chunk flags.
+__global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ws->count = 0ull;
+    for (; i < nsub; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
+}
+
+// The queued bins with the full rejection samplers (skipping bins of
+// sub-chunks left to k_raster_overflow).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_raster_deferred(RasterArgs A, const float* __restrict__ Q,
+                                                         float* __restrict__ grid,
+                                                         const RasterWs* __restrict__ ws,
+                                                         const uint8_t* __restrict__ flags,
+                                                         const DeferredBin* __restrict__ queue,
+                                                         unsigned long long cap) {
+    const unsigned long long cnt = min(ws->count, cap);
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const DeferredBin db = queue[i];
+        if (db.depo == kInvalid || flags[db.depo / kSub]) continue;
+        const uint32_t bin = (uint32_t)((int64_t)db.m * A.n_ticks + db.j);
+        const float v = bin_count_in<true>(MODE, Q[db.depo], (double)db.p, A.seed, db.depo, A.event,
+                                           bin, A.plane);
+        if (v != 0.f) atomicAdd(&grid[(int64_t)db.m * A.ld + db.j], v);
+    }
+}
+
+// Sub-chunks whose deferred bins did not fit in the queue: recompute their
+// regular depos' bins and draw the deferred ones with the full samplers.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_raster_overflow(RasterArgs A, const float* __restrict__ Q,
+                                                         const float* __restrict__ Tm,
+                                                         const float* __restrict__ X,
+                                                         const float* __restrict__ ST,
+                                                         const float* __restrict__ SX, int64_t n,
+                                                         float* __restrict__ grid,
+                                                         const uint8_t* __restrict__ flags) {
+    const int64_t nsub = (n + kSub - 1) / kSub;
+    for (int64_t sub = blockIdx.x; sub < nsub; sub += gridDim.x) {
+        if (!flags[sub]) continue;
+        for (int dd = 0; dd < kSub; ++dd) {
+            const int64_t gd = sub * kSub + dd;
+            if (gd >= n) break;
+            const float q = Q[gd], t = Tm[gd], x = X[gd], st = ST[gd], sx = SX[gd];
+            if (!depo_finite(q, t, x, st, sx)) continue;
+            const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+            if (!wt.n) continue;
+            const Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
+            if (!wx.n || wt.n > kMaxT || wx.n > kMaxX) continue;
+            const int ncell = wt.n * wx.n;
+            for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+                const int a = c / wt.n, b = c - a * wt.n;
+                const float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
+                const float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
+                const int j = wt.lo + b, m = wx.lo + a;
+                const double p = (double)(wtv * wxv);
+                const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                float v = bin_count_fast<MODE>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                if (v != v) {
+                    v = bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                    if (v != 0.f) atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                }
+            }
+        }
+    }
+}
+
+// Depos whose window exceeds the weight slots of k_raster (kMaxT ticks or
+// kMaxX impact rows): each workgroup scans a chunk of depos, and processes
+// the wide ones cooperatively, one cell per thread, weights per cell.
+template <int MODE>
+__global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterArgs A, const float* __restrict__ Q,
+                                                                const float* __restrict__ Tm,
+                                                                const float* __restrict__ X,
+                                                                const float* __restrict__ ST,
+                                                                const float* __restrict__ SX, int64_t n,
+                                                                float* __restrict__ grid) {
+    __shared__ int s_list[kRasterThreads];
+    __shared__ int s_n;
+    const int tid = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * kRasterThreads; base < n;
+         base += (int64_t)gridDim.x * kRasterThreads) {
+        if (tid == 0) s_n = 0;
+        __syncthreads();
+        int64_t d = base + tid;
+        if (d < n) {
+            float q = Q[d], t = Tm[d], x = X[d], st = ST[d], sx = SX[d];
+            if (depo_finite(q, t, x, st, sx)) {
+                Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+                Window wx = wt.n ? axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows)
+                                 : Window{0, 0, false};
+                if (wt.n && wx.n && (wt.n > kMaxT || wx.n > kMaxX)) s_list[atomicAdd(&s_n, 1)] = tid;
+            }
+        }
+        __syncthreads();
+        const int nw = s_n;
+        for (int i = 0; i < nw; ++i) {
+            int64_t gd = base + s_list[i];
+            float q = Q[gd], t = Tm[gd], x = X[gd], st = ST[gd], sx = SX[gd];
+            Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+            Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
+            int64_t ncell = (int64_t)wt.n * wx.n;
             for (int64_t c = tid; c < ncell; c += kRasterThreads) {
-                int a = (int)(c / ant), b = (int)(c - (int64_t)a * ant);
+                int a = (int)(c / wt.n), b = (int)(c - (int64_t)a * wt.n);
                 float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
                 float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
                 int j = wt.lo + b, m = wx.lo + a;
-                float v = cell_value<FLUCT>(A, q, wtv, wxv, (uint32_t)gd, m, j);
+                float v;
+                if (MODE == 0) {
+                    v = q * wtv * wxv;
+                } else {
+                    double p = (double)(wtv * wxv);
+                    uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                    v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                }
                 if (v != 0.f) atomicAdd(&grid[(int64_t)m * A.ld + j], v);
             }
         }
@@ -509,15 +894,44 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
 }
 
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
-                         const float* st, const float* sx, int64_t n, float* grid, hipStream_t s) {
+                         const float* st, const float* sx, int64_t n, float* grid, void* ws,
+                         size_t ws_bytes, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t nchunks = (n + kChunk - 1) / kChunk;
-    int64_t cap = 8 * (int64_t)device_cus();
-    dim3 grd((unsigned)(nchunks < cap ? nchunks : cap)), blk(kRasterThreads);
-    if (a.mode == 0)
-        hipLaunchKernelGGL(k_raster<false>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid);
-    else
-        hipLaunchKernelGGL(k_raster<true>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid);
+    const int64_t cap_blocks = 8 * (int64_t)device_cus();
+    const int64_t nsub = (n + kSub - 1) / kSub;
+    const int64_t nblk = (nsub + kWaves - 1) / kWaves;
+    dim3 grd((unsigned)(nblk < cap_blocks ? nblk : cap_blocks)), blk(kRasterThreads);
+    const int64_t nwide = (n + kRasterThreads - 1) / kRasterThreads;
+    dim3 gw((unsigned)(nwide < cap_blocks ? nwide : cap_blocks));
+    if (a.mode == 0) {
+        hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid, nullptr,
+                           nullptr, nullptr, 0ull);
+        hipLaunchKernelGGL(k_raster_wide<0>, gw, blk, 0, s, a, q, t, x, st, sx, n, grid);
+        return hipGetLastError();
+    }
+    const size_t fixed = raster_ws_fixed(n);
+    RasterWs* hdr = reinterpret_cast<RasterWs*>(ws);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(ws) + 256;
+    DeferredBin* queue = reinterpret_cast<DeferredBin*>(reinterpret_cast<char*>(ws) + fixed);
+    const unsigned long long cap = (unsigned long long)((ws_bytes - fixed) / sizeof(DeferredBin));
+    const int64_t rblk = (nsub + 255) / 256;
+    hipLaunchKernelGGL(k_raster_reset, dim3((unsigned)(rblk < cap_blocks ? (rblk > 0 ? rblk : 1) : cap_blocks)),
+                       dim3(256), 0, s, hdr, flags, nsub);
+    dim3 gsub((unsigned)(nsub < cap_blocks ? nsub : cap_blocks));
+#define LAR_FLUCT(M)                                                                              \
+    hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid, hdr, flags, queue, \
+                       cap);                                                                      \
+    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(256), 0, s, a, q,    \
+                       grid, hdr, flags, queue, cap);                                             \
+    hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, a, q, t, x, st, sx, n, grid,  \
+                       flags);                                                                    \
+    hipLaunchKernelGGL(k_raster_wide<M>, gw, blk, 0, s, a, q, t, x, st, sx, n, grid);
+    if (a.mode == 1) {
+        LAR_FLUCT(1)
+    } else {
+        LAR_FLUCT(2)
+    }
+#undef LAR_FLUCT
     return hipGetLastError();
 }
 

@@ -47,10 +47,12 @@ _P, _VP, _SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
 SIGNATURES = {
     "lar_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "lar_last_hip_error": ([], ctypes.c_int),
-    "lar_raster": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP], ctypes.c_int),
+    "lar_raster_workspace": ([_P(lar_plane), ctypes.c_int64, _P(lar_fluct), _P(_SZ)], ctypes.c_int),
+    "lar_raster": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP, _SZ, _VP],
+                   ctypes.c_int),
     "lar_fftconv_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
     "lar_fftconv": ([_P(lar_plane), _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
-    "lar_sim_plane_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_sim_plane_workspace": ([_P(lar_plane), ctypes.c_int64, _P(lar_fluct), _P(_SZ)], ctypes.c_int),
     "lar_sim_plane": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP, _VP, _SZ,
                        _VP], ctypes.c_int),
     "lar_response_spectrum_workspace": ([_P(lar_plane), ctypes.c_int32, ctypes.c_int32, _P(_SZ)],
@@ -149,11 +151,19 @@ def workspace(nbytes, device="cuda"):
 
 # ---------------------------------------------------------------- calls
 
-def raster(plane, depos: DeviceDepos, nsigma, fluct, grid, stream=None):
+def raster_workspace(plane, n_depos, fluct) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_raster_workspace(ctypes.byref(make_plane(plane)), int(n_depos), _fluct(fluct),
+                                       ctypes.byref(n)), "lar_raster_workspace")
+    return n.value
+
+
+def raster(plane, depos: DeviceDepos, nsigma, fluct, grid, ws=None, stream=None):
     pl = make_plane(plane)
     ds = depos.struct()
+    wsp, wsn = (None, 0) if ws is None else (_ptr(ws), ws.numel())
     _check(_lib().lar_raster(ctypes.byref(pl), ctypes.byref(ds), float(nsigma), _fluct(fluct), _ptr(grid),
-                             _stream(stream)), "lar_raster")
+                             wsp, wsn, _stream(stream)), "lar_raster")
 
 
 def fftconv_workspace(plane) -> int:
@@ -169,10 +179,10 @@ def fftconv(plane, grid, resp, wave, ws, stream=None):
                               _stream(stream)), "lar_fftconv")
 
 
-def sim_plane_workspace(plane) -> int:
+def sim_plane_workspace(plane, n_depos=0, fluct=None) -> int:
     n = ctypes.c_size_t(0)
-    _check(_lib().lar_sim_plane_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)),
-           "lar_sim_plane_workspace")
+    _check(_lib().lar_sim_plane_workspace(ctypes.byref(make_plane(plane)), int(n_depos), _fluct(fluct),
+                                          ctypes.byref(n)), "lar_sim_plane_workspace")
     return n.value
 
 

@@ -46,6 +46,11 @@ def test_workspace_queries_and_size_checks(lar):
     ld = (3073 + 15) // 16 * 16
     assert lar.fftconv_workspace(P) == 4800 * ld * 8 + (480 * ld * 8 + 255) // 256 * 256
     assert lar.sim_plane_workspace(P) == 4800 * 6000 * 4 + lar.fftconv_workspace(P)
+    assert lar.raster_workspace(P, 1000, None) == 0
+    fixed = 256 + ((1000 + 15) // 16 + 255) // 256 * 256
+    assert lar.raster_workspace(P, 1000, (1, 0, 0, 0)) == fixed + (1000 * 16 + 4096) * 16
+    assert (lar.sim_plane_workspace(P, 1000, (2, 0, 0, 0))
+            == lar.sim_plane_workspace(P) + lar.raster_workspace(P, 1000, (2, 0, 0, 0)))
     for bad in (dict(nt_fft=6000 + 2 * 7), dict(nt_fft=5999), dict(nw_fft=500), dict(nw_fft=400),
                 dict(nt_fft=32768), dict(nw_fft=1152)):
         Q = inputs.cfg1_plane()
@@ -60,15 +65,21 @@ def test_host_side_argument_errors(lar):
     L = lar.lib()
     P = lar.make_plane(inputs.cfg0_plane())
     d = lar.lar_depos(None, None, None, None, None, -1)
-    assert L.lar_raster(ctypes.byref(P), ctypes.byref(d), 3.0, None, None, None) == lar.LAR_EINVAL
+    R = L.lar_raster
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, None, None, None, 0, None) == lar.LAR_EINVAL
     d = lar.lar_depos(None, None, None, None, None, 0)
-    assert L.lar_raster(ctypes.byref(P), ctypes.byref(d), 3.0, None, None, None) == lar.LAR_OK
-    assert L.lar_raster(ctypes.byref(P), ctypes.byref(d), 0.0, None, None, None) == lar.LAR_EINVAL
-    assert L.lar_raster(None, ctypes.byref(d), 3.0, None, None, None) == lar.LAR_EINVAL
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, None, None, None, 0, None) == lar.LAR_OK
+    assert R(ctypes.byref(P), ctypes.byref(d), 0.0, None, None, None, 0, None) == lar.LAR_EINVAL
+    assert R(None, ctypes.byref(d), 3.0, None, None, None, 0, None) == lar.LAR_EINVAL
     f = lar.lar_fluct(3, 0, 0, 0, 0)
-    assert L.lar_raster(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None) == lar.LAR_EINVAL
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_EINVAL
     f = lar.lar_fluct(1, 0, 300, 0, 0)
-    assert L.lar_raster(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None) == lar.LAR_EINVAL
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_EINVAL
+    one = ctypes.c_void_p(256)
+    d = lar.lar_depos(one, one, one, one, one, 10)
+    f = lar.lar_fluct(1, 0, 0, 0, 0)
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), one, None, 0, None) == lar.LAR_EWORKSPACE
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), one, one, 255, None) == lar.LAR_EWORKSPACE
     assert L.lar_fftconv(ctypes.byref(P), None, None, None, None, 0, None) == lar.LAR_EINVAL
     one = ctypes.c_void_p(256)
     assert L.lar_fftconv(ctypes.byref(P), one, one, one, None, 0, None) == lar.LAR_EWORKSPACE
