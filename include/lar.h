@@ -134,6 +134,30 @@ int lar_sim_plane(const lar_plane *plane, const lar_depos *depos, float nsigma,
                   const lar_fluct *fluct, const float *resp, float *wave,
                   void *workspace, size_t ws_bytes, void *stream);
 
+/* Adjoint of lar_fftconv (gradients of a loss L through wave = conv(grid,
+ * resp); no paper counterpart, the transpose of Eq. (2)).  With G =
+ * dL/dwave [n_wires][n_ticks] and FT2/IFT2 as in lar_fftconv:
+ *  grid_grad[w*n_imp + k][j] = crop IFT2( conj(resp[k]) * FT2(G) )
+ *      (OVERWRITTEN; exact for any resp),
+ *  resp_grad[k][p][f] += c_f/(nw_fft*nt_fft) * FT2(G)[p][f] * conj(FT2(S_k)[p][f])
+ *      (ACCUMULATED, as d/dRe + i d/dIm; c_f = 1 at f = 0 and nt_fft/2, else 2).
+ * Either output may be NULL; grid may be NULL when resp_grad is. */
+int lar_fftconv_backward_workspace(const lar_plane *plane, size_t *bytes);
+int lar_fftconv_backward(const lar_plane *plane, const float *grid, const float *resp,
+                         const float *wave_grad, float *grid_grad, float *resp_grad,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* Adjoint of the mean raster (no paper counterpart): for every depo the
+ * gradient of L = sum grid_grad * S with respect to q, t, x, sigma_t,
+ * sigma_x, windows held fixed (the patch is recomputed, not stored):
+ *  dq = sum G wt wx, dt = q sum G (dwt/dt) wx, dsigma_t = q sum G (dwt/dsigma_t) wx,
+ *  and likewise for x and sigma_x, with dw/dmu = -(phi(z_b) - phi(z_a))/sigma and
+ *  dw/dsigma = -(z_b phi(z_b) - z_a phi(z_a))/sigma.  Point axes and skipped
+ * depos get zero.  Outputs: n floats each, OVERWRITTEN.  No workspace. */
+int lar_raster_backward(const lar_plane *plane, const lar_depos *depos, float nsigma,
+                        const float *grid_grad, float *dq, float *dt, float *dx,
+                        float *dsigma_t, float *dsigma_x, void *stream);
+
 /* Response spectrum from a time-domain response (detector response R of
  * Eq. (1), paper Sec. 2.1): r_time[k][dw + half_w][tau], k < n_imp,
  * |dw| <= half_w, tau < n_rt, placed at wire index dw mod nw_fft and tick

@@ -253,7 +253,8 @@ static double lo_ipow(double x, double n)
 }
 
 /* Binomial(n, p) by sequential inversion from k = 0 (p <= 1/2, n*p < 10):
- * f(0) = (1-p)^n, f(k) = f(k-1) * ((n+1) r / k - r) with r = p/(1-p). */
+ * f(0) = (1-p)^n, f(k) = f(k-1) * (g * (1/k) - r) with r = p/(1-p),
+ * g = (n+1) r and 1/k the correctly rounded reciprocal. */
 static double lo_binom_inv(double n, double p, lo_stream *s)
 {
     double q = 1.0 - p;
@@ -269,7 +270,7 @@ static double lo_binom_inv(double n, double p, lo_stream *s)
             if (k >= n || k > 110.0) break;       /* numerical tail: redraw */
             u = u - f;
             k = k + 1.0;
-            f = f * (g / k - ratio);
+            f = f * (g * (1.0 / k) - ratio);
         }
     }
     return floor(n * p);
@@ -308,14 +309,19 @@ static double lo_binom_btrd(double n, double p, lo_stream *s)
         if (k < 0.0 || k > n) continue;
         v = v * alpha / (a / (us * us) + b);
         double km = fabs(k - m);
-        if (km <= 15.0) {                         /* explicit pmf ratio f(k)/f(m) */
-            double f = 1.0;
+        if (km <= 15.0) {
+            /* explicit pmf ratio f(k)/f(m) = prod (nr/i - r), as the product
+             * of the numerators (nr - r i) over the product of the i's */
+            double num = 1.0, den = 1.0;
             if (m < k) {
-                for (double i = m + 1.0; i <= k; i = i + 1.0) f = f * (nr / i - r);
+                for (double i = m + 1.0; i <= k; i = i + 1.0) { num = num * (nr - r * i); den = den * i; }
+                if (v * den <= num) return k;
             } else if (m > k) {
-                for (double i = k + 1.0; i <= m; i = i + 1.0) v = v * (nr / i - r);
+                for (double i = k + 1.0; i <= m; i = i + 1.0) { num = num * (nr - r * i); den = den * i; }
+                if (v * num <= den) return k;
+            } else if (v <= 1.0) {
+                return k;
             }
-            if (v <= f) return k;
             continue;
         }
         v = log(v);                               /* squeeze on log scale */

@@ -371,6 +371,144 @@ hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_im
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------- wire pass, adjoint
+//
+// For a tile of C time-frequency columns: Gh = FFT over wires of the
+// waveform-gradient spectrum Gt (rows w < n_wires, zero padded).  For each
+// impact offset k:
+//  - response gradient (dR != null): Sk = FFT over wires of the grid
+//    spectrum rows w*n_imp + k, dR[k] += resp_scale c_f Gh conj(Sk), with
+//    c_f = 1 at f = 0 and f = Tf/2 and 2 elsewhere;
+//  - grid gradient (want_grid): conj(R[k]) Gh, inverse FFT over wires,
+//    written over the same rows of S (each tile reads them first).
+template <int VPT, int C, int NT>
+__global__ __launch_bounds__(NT) void k_wire_adjoint(
+    const float2* __restrict__ Gt, int64_t ldG, float2* __restrict__ S, int64_t ldS, int n_wires,
+    int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R, float2* __restrict__ dR,
+    int want_grid, float resp_scale) {
+    extern __shared__ float2 lds[];
+    const int Wf = plan.n, tid = threadIdx.x, T = blockDim.x;
+    float2* A = lds;
+    float2* tw = lds + Wf * C;
+    fill_full_table(tw, Wf, tid, T);
+    const TwFull twf{tw};
+    const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const int nel = Wf * C;
+    float2 gh[VPT];
+    // ---- Gh
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int e = tid + i * T;
+        const int p = e / C, f = f0 + e % C;
+        const bool ok = e < nel && p < n_wires && f < F;
+        const float2 v = Gt[(int64_t)min(p, n_wires - 1) * ldG + min(f, F - 1)];
+        gh[i] = ok ? v : make_float2(0.f, 0.f);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int e = tid + i * T;
+        if (e < nel) A[e] = gh[i];
+    }
+    lds_barrier();
+    fft_lds<VPT, C>(A, plan, tid, T, twf, false);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int e = tid + i * T;
+        if (e < nel) gh[i] = A[e];
+    }
+    for (int k = 0; k < n_imp; ++k) {
+        if (dR) {
+            float2 v[VPT];
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = e / C, f = f0 + e % C;
+                const bool ok = e < nel && p < n_wires && f < F;
+                const float2 x = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + min(f, F - 1)];
+                v[i] = ok ? x : make_float2(0.f, 0.f);
+            }
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                if (e < nel) A[e] = v[i];
+            }
+            lds_barrier();
+            fft_lds<VPT, C>(A, plan, tid, T, twf, false);
+            float2* dRk = dR + (int64_t)k * Wf * F;
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = e / C, f = f0 + e % C;
+                if (e < nel && f < F) {
+                    const float cf = (f == 0 || f == nyq) ? resp_scale : 2.f * resp_scale;
+                    const float2 sk = A[e];
+                    const float2 g = cmulc(gh[i], sk);   // Gh conj(Sk)
+                    float2* o = dRk + (int64_t)p * F + f;
+                    float2 cur = *o;
+                    cur.x += cf * g.x;
+                    cur.y += cf * g.y;
+                    *o = cur;
+                }
+            }
+        }
+        if (want_grid) {
+            const float2* Rk = R + (int64_t)k * Wf * F;
+            float2 r[VPT];
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = min(e / C, Wf - 1), f = min(f0 + e % C, F - 1);
+                r[i] = Rk[(int64_t)p * F + f];
+            }
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                if (e < nel) A[e] = cmulc(gh[i], r[i]);   // conj(R) Gh
+            }
+            lds_barrier();
+            fft_lds<VPT, C>(A, plan, tid, T, twf, true);
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = e / C, f = f0 + e % C;
+                if (e < nel && p < n_wires && f < F) S[(int64_t)(p * n_imp + k) * ldS + f] = A[e];
+            }
+        }
+    }
+}
+
+template <int VPT, int C, int NT>
+static hipError_t wire_adj_launch(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
+                                  int n_imp, int F, int nyq, const FftPlan& plan, const float2* R,
+                                  float2* dR, bool want_grid, float scale, hipStream_t s) {
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
+    set_lds(k_wire_adjoint<VPT, C, NT>, lds);
+    dim3 grid((F + C - 1) / C), block(NT);
+    hipLaunchKernelGGL((k_wire_adjoint<VPT, C, NT>), grid, block, lds, s, Gt, ldG, S, ldS, n_wires,
+                       n_imp, F, nyq, plan, R, dR, want_grid ? 1 : 0, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
+                               int n_imp, int nw_fft, int nt_fft, const float2* R, float2* dR,
+                               bool want_grid, float resp_scale, hipStream_t s) {
+    FftPlan plan;
+    if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
+    const int F = nt_fft / 2 + 1, nyq = nt_fft / 2;
+#define LAR_WADJ(V)                                                                              \
+    return wire_adj_launch<V, 8, 512>(Gt, ldG, S, ldS, n_wires, n_imp, F, nyq, plan, R, dR,      \
+                                      want_grid, resp_scale, s);
+    if (nw_fft <= 128) LAR_WADJ(2)
+    if (nw_fft <= 256) LAR_WADJ(4)
+    if (nw_fft <= 512) LAR_WADJ(8)
+    if (nw_fft <= 1024) LAR_WADJ(16)
+#undef LAR_WADJ
+    return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------- response spectrum
 //
 // rows: time spectra [n_imp][nrw][ld_rows] of the response rows (dw = row -

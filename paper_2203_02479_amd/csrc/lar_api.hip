@@ -245,6 +245,73 @@ int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
     return fftconv_impl(plane, grid, resp, wave, w + grid_bytes(plane), s);
 }
 
+// fftconv backward workspace: [FT of wave_grad rows: N_w x ld][grid rows: R_rows x ld]
+static size_t fftconv_bwd_bytes(const lar_plane* p) {
+    size_t ld = (size_t)spec_ld(p);
+    return align_up((size_t)p->n_wires * ld * sizeof(float2), 256) +
+           align_up((size_t)p->n_wires * p->n_imp * ld * sizeof(float2), 256);
+}
+
+int lar_fftconv_backward_workspace(const lar_plane* plane, size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = fftconv_bwd_bytes(plane);
+    return LAR_OK;
+}
+
+int lar_fftconv_backward(const lar_plane* p, const float* grid, const float* resp,
+                         const float* wave_grad, float* grid_grad, float* resp_grad, void* ws,
+                         size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(p))) return st;
+    if (!resp || !wave_grad || (resp_grad && !grid)) return LAR_EINVAL;
+    if (!grid_grad && !resp_grad) return LAR_OK;
+    if (!ws || ws_bytes < fftconv_bwd_bytes(p) || reinterpret_cast<uintptr_t>(ws) % 256)
+        return LAR_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ld = spec_ld(p);
+    const int rows = p->n_wires * p->n_imp;
+    float2* Gt = reinterpret_cast<float2*>(ws);
+    float2* Sb = reinterpret_cast<float2*>(reinterpret_cast<char*>(ws) +
+                                           align_up((size_t)p->n_wires * ld * sizeof(float2), 256));
+    const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
+    LAR_TRY(launch_r2c_rows(wave_grad, p->n_ticks, p->n_ticks, p->n_wires, p->nt_fft, Gt, ld, s));
+    if (resp_grad) LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sb, ld, s));
+    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
+                                reinterpret_cast<const float2*>(resp),
+                                reinterpret_cast<float2*>(resp_grad), grid_grad != nullptr, scale, s));
+    if (grid_grad)
+        LAR_TRY(launch_c2r_rows(Sb, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s));
+    return LAR_OK;
+}
+
+int lar_raster_backward(const lar_plane* plane, const lar_depos* depos, float nsigma,
+                        const float* grid_grad, float* dq, float* dt, float* dx, float* dsigma_t,
+                        float* dsigma_x, void* stream) {
+    int st;
+    if ((st = check_plane(plane))) return st;
+    if ((st = check_depos(depos))) return st;
+    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    if (depos->n == 0) return LAR_OK;
+    if (!grid_grad || !dq || !dt || !dx || !dsigma_t || !dsigma_x) return LAR_EINVAL;
+    RasterArgs a;
+    a.n_ticks = plane->n_ticks;
+    a.n_rows = plane->n_wires * plane->n_imp;
+    a.ld = plane->n_ticks;
+    a.org_t = (double)plane->t0;
+    a.wd_t = (double)plane->tick;
+    a.org_x = (double)plane->x0 - (double)plane->pitch / 2.0;
+    a.wd_x = (double)plane->pitch / (double)plane->n_imp;
+    a.nsig = (double)nsigma;
+    a.mode = 0;
+    a.event = a.plane = 0u;
+    a.seed = 0ull;
+    LAR_TRY(launch_raster_bwd(a, depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x,
+                              depos->n, grid_grad, dq, dt, dx, dsigma_t, dsigma_x, (hipStream_t)stream));
+    return LAR_OK;
+}
+
 // response spectrum workspace: time spectra of the n_imp*(2H+1) response rows
 static size_t respspec_bytes(const lar_plane* p, int half_w) {
     return align_up((size_t)p->n_imp * (2 * half_w + 1) * spec_ld(p) * sizeof(float2), 256);

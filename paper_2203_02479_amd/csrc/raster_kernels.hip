@@ -130,11 +130,12 @@ __device__ __forceinline__ double ipow_n(double x, double n) {
 }
 
 // Binomial by inversion from k = 0 (p <= 1/2, n p < 10): f(0) = (1-p)^n,
-// f(k) = f(k-1) ((n+1) r / k - r), r = p/(1-p).  When n p < 1 the first
+// f(k) = f(k-1) ((n+1) r (1/k) - r), r = p/(1-p), 1/k correctly rounded.  When n p < 1 the first
 // uniform is compared with a lower bound of f(0) first: (1-p)^n >= 1 - n p
 // (Bernoulli), minus a margin above the rounding of q and of the powering,
 // so the early return of 0 happens only where the full test returns 0.
-__device__ double binom_inversion(double n, double p, PhiloxStream& s) {
+__device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStream& s,
+                                                  const double* rtab) {
 #pragma clang fp contract(off)
     double q = 1.0 - p;
     double ratio = p / q;
@@ -152,10 +153,35 @@ __device__ double binom_inversion(double n, double p, PhiloxStream& s) {
             if (k >= n || k > 110.0) break;
             u = u - f;
             k = k + 1.0;
-            f = f * (g / k - ratio);
+            // 1/k correctly rounded: from the table when given, else divided
+            const double ik = rtab ? rtab[(int)k] : 1.0 / k;
+            f = f * (g * ik - ratio);
         }
     }
     return floor(n * p);
+}
+
+// BTRD's explicit test v <= f(k)/f(m) for |k - m| <= 15, with the pmf ratio
+// prod (nr/i - r) written as the product of the numerators (nr - r i) over
+// the product of the i's (no division).
+__device__ __forceinline__ int btrd_ratio_accept(double v, double k, double m, double nr, double r) {
+#pragma clang fp contract(off)
+    double num = 1.0, den = 1.0;
+    if (m < k) {
+        for (double i = m + 1.0; i <= k; i = i + 1.0) {
+            num = num * (nr - r * i);
+            den = den * i;
+        }
+        return v * den <= num;
+    }
+    if (m > k) {
+        for (double i = k + 1.0; i <= m; i = i + 1.0) {
+            num = num * (nr - r * i);
+            den = den * i;
+        }
+        return v * num <= den;
+    }
+    return v <= 1.0;
 }
 
 // Binomial by BTRD, transformed rejection with decomposition (p <= 1/2, n p >= 10).
@@ -199,13 +225,7 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s) {
         v = v * alpha / (a / (us * us) + b);
         double km = fabs(k - m);
         if (km <= 15.0) {
-            double f = 1.0;
-            if (m < k) {
-                for (double i = m + 1.0; i <= k; i = i + 1.0) f = f * (nr / i - r);
-            } else if (m > k) {
-                for (double i = k + 1.0; i <= m; i = i + 1.0) v = v * (nr / i - r);
-            }
-            if (v <= f) return k;
+            if (btrd_ratio_accept(v, k, m, nr, r)) return k;
             continue;
         }
         v = log(v);
@@ -268,9 +288,14 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s) {
     return floor(lam);
 }
 
-// First try of BTRD restricted to its fast acceptance region (the same
-// operations as the full sampler's first try): the count, or -1 when the
-// full sampler has to run.
+// BTRD without its logarithmic acceptance test: the same tries, the same
+// uniforms and the same decisions as binom_btrd for as long as every try is
+// decided by the fast region, the bounds test or the explicit pmf ratio
+// (|k - m| <= 15); returns -1 as soon as a try needs the log-scale test, or
+// after kFastTries tries.  The full sampler then redraws the bin from its
+// counter and reaches the same result.
+static constexpr int kFastTries = 4;
+
 __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double npq = n * p * (1.0 - p);
@@ -280,27 +305,58 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
     double c = n * p + 0.5;
     double vr = 0.92 - 4.2 / b;
     double urvr = 0.86 * vr;
-    double v = next_uniform(s);
-    if (v <= urvr) {
-        double u = v / vr - 0.43;
-        return floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+    double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
+    bool slow_ready = false;
+    for (int tries = 0; tries < kFastTries; ++tries) {
+        double v = next_uniform(s);
+        double u;
+        if (v <= urvr) {
+            u = v / vr - 0.43;
+            return floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
+        }
+        if (!slow_ready) {
+            m = floor((n + 1.0) * p);
+            r = p / (1.0 - p);
+            nr = (n + 1.0) * r;
+            alpha = (2.83 + 5.1 / b) * spq;
+            slow_ready = true;
+        }
+        if (v >= vr) {
+            u = next_uniform(s) - 0.5;
+        } else {
+            u = v / vr - 0.93;
+            u = copysign(0.5, u) - u;
+            v = next_uniform(s) * vr;
+        }
+        double us = 0.5 - fabs(u);
+        double k = floor((2.0 * a / us + b) * u + c);
+        if (k < 0.0 || k > n) continue;
+        v = v * alpha / (a / (us * us) + b);
+        double km = fabs(k - m);
+        if (km > 15.0) return -1.0;
+        if (btrd_ratio_accept(v, k, m, nr, r)) return k;
     }
     return -1.0;
 }
 
-// First try of PTRS restricted to its immediate acceptance (us >= 0.07 and
-// v <= v_r): the count, or -1 when the full sampler has to run.
+// PTRS without its logarithmic acceptance test (same tries and decisions as
+// poisson_ptrs while each try is decided by the immediate acceptance or the
+// cheap rejection); -1 when a try needs the log test or after kFastTries.
 __device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double slam = sqrt(lam);
     double b = 0.931 + 2.53 * slam;
     double a = -0.059 + 0.02483 * b;
     double vr = 0.9277 - 3.6224 / (b - 2.0);
-    double u = next_uniform(s) - 0.5;
-    double v = next_uniform(s);
-    double us = 0.5 - fabs(u);
-    double k = floor((2.0 * a / us + b) * u + lam + 0.43);
-    if (us >= 0.07 && v <= vr) return k;
+    for (int tries = 0; tries < kFastTries; ++tries) {
+        double u = next_uniform(s) - 0.5;
+        double v = next_uniform(s);
+        double us = 0.5 - fabs(u);
+        double k = floor((2.0 * a / us + b) * u + lam + 0.43);
+        if (us >= 0.07 && v <= vr) return k;
+        if (k < 0.0 || (us < 0.013 && v > us)) continue;
+        return -1.0;
+    }
     return -1.0;
 }
 
@@ -309,7 +365,8 @@ __device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s)
 // sampler (bin_count_in<true>, which redraws it from the same counter).
 template <int MODE>
 __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
-                                                uint32_t event, uint32_t bin, uint32_t plane) {
+                                                uint32_t event, uint32_t bin, uint32_t plane,
+                                                const double* rtab = nullptr) {
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
@@ -325,7 +382,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
         } else {
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
-            double k = (n * pp < 10.0) ? binom_inversion(n, pp, s) : binom_btrd_fast(n, pp, s);
+            double k = (n * pp < 10.0) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast(n, pp, s);
             if (k < 0.0) return __builtin_nanf("");
             r = flip ? n - k : k;
         }
@@ -377,7 +434,7 @@ __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint6
         } else {
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
-            double k = REJECT ? binom_btrd(n, pp, s) : binom_inversion(n, pp, s);
+            double k = REJECT ? binom_btrd(n, pp, s) : binom_inversion(n, pp, s, nullptr);
             r = flip ? n - k : k;
         }
     } else {
@@ -579,6 +636,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
     __shared__ float s_q[kWaves][kSub];
     __shared__ int s_off[kWaves][FLUCT ? kSub + 1 : 1];
     __shared__ uint16_t s_queue[kWaves][FLUCT ? kWaveQueue : 1];   // (depo:4 | row:5 | tick:4)
+    __shared__ uint16_t s_list[kWaves][2][FLUCT ? 128 : 1];          // cells by sampler regime
+    __shared__ double s_rcp[FLUCT ? 112 : 1];                        // 1/k, k < 112
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float* W = s_w[wv];
@@ -589,6 +648,10 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
     int* nx_ = s_meta[wv][3];
     float* q_ = s_q[wv];
     for (int i = lane; i < kWaveTile; i += 64) tile[i] = 0.f;
+    if (FLUCT) {
+        for (int i = threadIdx.x; i < 112; i += kRasterThreads) s_rcp[i] = i ? 1.0 / (double)i : 0.0;
+        __syncthreads();
+    }
 
     const int64_t nsub = (n + kSub - 1) / kSub;
     for (int64_t sub = (int64_t)blockIdx.x * kWaves + wv; sub < nsub;
@@ -678,80 +741,116 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
                 asm volatile("" ::: "memory");
             }
         } else {
-            // ---- fluctuated patches: lanes flat over the sub-chunk's cells
+            // ---- fluctuated patches.  Cells are classified 64 at a time by
+            // sampler regime into two wave-local stacks (inversion and
+            // rejection), and each stack is drawn in batches of 64 so that a
+            // wave runs one sampler at a time.  Rejection-regime bins that
+            // reach the log-scale test are queued for k_raster_deferred.
             const int total = s_off[wv][kSub];
-            int nq = 0;   // buffered deferred bins (wave-uniform)
+            uint16_t* LI = s_list[wv][0];
+            uint16_t* LR = s_list[wv][1];
+            int nI = 0, nR = 0, nq = 0;   // wave-uniform stack and queue sizes
             int d = 0;
-            for (int c0 = 0; c0 < total; c0 += 64) {
-                const int c = c0 + lane;
-                int m = 0, j = 0, todo = -1;
-                float v = 0.f;
-                bool defer = false;
-                int code = 0;
-                if (c < total) {
-                    while (s_off[wv][d + 1] <= c) ++d;
-                    const int ant = abs(nt_[d]);
-                    const int local = c - s_off[wv][d];
-                    const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
-                    const int b = local - a * ant;
-                    const float* w = W + d * kSlot;
-                    j = jlo_[d] + b;
-                    m = mlo_[d] + a;
-                    const double p = (double)(w[b] * w[kMaxT + a]);
-                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                    v = bin_count_fast<MODE>(q_[d], p, A.seed, (uint32_t)(base + d), A.event, bin,
-                                             A.plane);
-                    if (v != v) {
-                        defer = true;
+            int c0 = 0;
+            while (c0 < total || nI > 0 || nR > 0) {
+                if (c0 < total) {
+                    const int c = c0 + lane;
+                    bool isI = false, isR = false;
+                    int code = 0;
+                    if (c < total) {
+                        while (s_off[wv][d + 1] <= c) ++d;
+                        const int ant = abs(nt_[d]);
+                        const int local = c - s_off[wv][d];
+                        const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
+                        const int b = local - a * ant;
+                        const float* w = W + d * kSlot;
+                        const double p = (double)(w[b] * w[kMaxT + a]);
                         code = (d << 9) | (a << 4) | b;
-                    } else if (v != 0.f) {
-                        todo = d;
+                        isR = rejection_regime(MODE, q_[d], p);
+                        isI = !isR;
                     }
+                    const uint64_t mI = __ballot(isI), mR = __ballot(isR);
+                    const uint64_t below = (1ull << lane) - 1;
+                    if (isI) LI[nI + __popcll(mI & below)] = (uint16_t)code;
+                    if (isR) LR[nR + __popcll(mR & below)] = (uint16_t)code;
+                    nI += __popcll(mI);
+                    nR += __popcll(mR);
+                    c0 += 64;
                 }
-                const uint64_t dm = __ballot(defer);
-                if (defer) s_queue[wv][nq + __popcll(dm & ((1ull << lane) - 1))] = (uint16_t)code;
-                nq += __popcll(dm);
-                // add the drawn counts, the lanes of one depo at a time
-                for (;;) {
-                    const int first = wave_min(todo < 0 ? INT_MAX : todo);
-                    if (first == INT_MAX) break;
-                    if (todo == first) {
-                        if (use_tile)
-                            tile[(m - mmin) * span_t + (j - jmin)] += v;
-                        else
-                            atomicAdd(&grid[(int64_t)m * A.ld + j], v);
-                        todo = -1;
-                    }
-                    asm volatile("" ::: "memory");
-                }
-                // move buffered bins to the workspace queue when the next
-                // instruction could overflow the buffer, and at the end
-                if (nq > kWaveQueue - 64 || (c0 + 64 >= total && nq > 0)) {
-                    wave_lds_sync();
-                    unsigned long long gb = 0;
-                    if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
-                    gb = __shfl(gb, 0, 64);
-                    const bool fits = gb + (unsigned long long)nq <= cap;
-                    for (int e = lane; e < nq; e += 64) {
-                        const unsigned long long slot = gb + (unsigned long long)e;
-                        if (slot >= cap) continue;
-                        DeferredBin db;
-                        if (fits) {
-                            const int cd = s_queue[wv][e];
-                            const int dd = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                const bool tail = c0 >= total;
+                for (int which = 0; which < 2; ++which) {
+                    uint16_t* L = which ? LR : LI;
+                    int& nL = which ? nR : nI;
+                    while (nL >= 64 || (tail && nL > 0)) {
+                        wave_lds_sync();
+                        const int cnt = min(nL, 64);
+                        int m = 0, j = 0, todo = -1, code = 0;
+                        bool defer = false;
+                        float v = 0.f;
+                        if (lane < cnt) {
+                            code = L[nL - cnt + lane];
+                            const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
                             const float* w = W + dd * kSlot;
-                            db.depo = (uint32_t)(base + dd);
-                            db.m = (uint32_t)(mlo_[dd] + a);
-                            db.j = (uint32_t)(jlo_[dd] + b);
-                            db.p = w[b] * w[kMaxT + a];
-                        } else {
-                            db.depo = kInvalid; db.m = 0; db.j = 0; db.p = 0.f;
+                            j = jlo_[dd] + b;
+                            m = mlo_[dd] + a;
+                            const double p = (double)(w[b] * w[kMaxT + a]);
+                            const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                            v = bin_count_fast<MODE>(q_[dd], p, A.seed, (uint32_t)(base + dd), A.event,
+                                                     bin, A.plane, s_rcp);
+                            if (v != v) {
+                                defer = true;
+                            } else if (v != 0.f) {
+                                todo = dd;
+                            }
                         }
-                        queue[slot] = db;
+                        nL -= cnt;
+                        const uint64_t dm = __ballot(defer);
+                        if (defer) s_queue[wv][nq + __popcll(dm & ((1ull << lane) - 1))] = (uint16_t)code;
+                        nq += __popcll(dm);
+                        // add the drawn counts, the lanes of one depo at a time
+                        for (;;) {
+                            const int first = wave_min(todo < 0 ? INT_MAX : todo);
+                            if (first == INT_MAX) break;
+                            if (todo == first) {
+                                if (use_tile)
+                                    tile[(m - mmin) * span_t + (j - jmin)] += v;
+                                else
+                                    atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                                todo = -1;
+                            }
+                            asm volatile("" ::: "memory");
+                        }
+                        // move queued bins to the workspace when the next batch
+                        // could overflow the buffer, and at the end
+                        const bool last = tail && nI == 0 && nR == 0;
+                        if (nq > kWaveQueue - 64 || (last && nq > 0)) {
+                            wave_lds_sync();
+                            unsigned long long gb = 0;
+                            if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
+                            gb = __shfl(gb, 0, 64);
+                            const bool fits = gb + (unsigned long long)nq <= cap;
+                            for (int e = lane; e < nq; e += 64) {
+                                const unsigned long long slot = gb + (unsigned long long)e;
+                                if (slot >= cap) continue;
+                                DeferredBin db;
+                                if (fits) {
+                                    const int cd = s_queue[wv][e];
+                                    const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                                    const float* w = W + dq * kSlot;
+                                    db.depo = (uint32_t)(base + dq);
+                                    db.m = (uint32_t)(mlo_[dq] + a);
+                                    db.j = (uint32_t)(jlo_[dq] + b);
+                                    db.p = w[b] * w[kMaxT + a];
+                                } else {
+                                    db.depo = kInvalid; db.m = 0; db.j = 0; db.p = 0.f;
+                                }
+                                queue[slot] = db;
+                            }
+                            if (!fits && lane == 0) flags[sub] = 1;
+                            nq = 0;
+                            wave_lds_sync();
+                        }
                     }
-                    if (!fits && lane == 0) flags[sub] = 1;
-                    nq = 0;
-                    wave_lds_sync();
                 }
             }
         }
@@ -891,6 +990,106 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterArgs A, co
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------- adjoint raster
+//
+// Gradients of L = sum_{m,j} G[m][j] S[m][j] with respect to each depo's q,
+// t, x, sigma_t, sigma_x for the mean patch, windows held fixed:
+//   dw/dmu = -(phi(z_b) - phi(z_a))/sigma, dw/dsigma = -(z_b phi(z_b) - z_a phi(z_a))/sigma
+// (phi the standard normal density).  One thread per depo recomputes its
+// windows (same FP64 decisions as the forward raster) and weights, and
+// gathers G over the patch row by row:
+//   dq = sum_a wx_a r_a, dt = q sum_a wx_a s_a, dsigma_t = q sum_a wx_a u_a,
+//   dx = q sum_a dwx_a r_a, dsigma_x = q sum_a dswx_a r_a
+// with r_a, s_a, u_a the row's G sums weighted by wt, dwt/dmu, dwt/dsigma.
+
+__device__ __forceinline__ float normal_pdf(float z) {
+#pragma clang fp contract(off)
+    return 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// weight and its two derivatives for bin i of a window
+__device__ __forceinline__ void weight_grads(double mu, double sg, double org, double wd,
+                                             const Window& win, int i, float& w, float& dmu,
+                                             float& dsg) {
+    if (win.point) {
+        w = 1.f; dmu = 0.f; dsg = 0.f;
+        return;
+    }
+    const double inv = 1.0 / sg;
+    const float za = edge_z(org, wd, win.lo + i, mu, inv);
+    const float zb = edge_z(org, wd, win.lo + i + 1, mu, inv);
+    w = bin_weight(za, zb, normal_tail(za), normal_tail(zb));
+    const float pa = normal_pdf(za), pb = normal_pdf(zb);
+    const float is = (float)inv;
+    dmu = -(pb - pa) * is;
+    dsg = -(zb * pb - za * pa) * is;
+}
+
+__global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs A, const float* __restrict__ Q,
+                                                    const float* __restrict__ Tm,
+                                                    const float* __restrict__ X,
+                                                    const float* __restrict__ ST,
+                                                    const float* __restrict__ SX, int64_t n,
+                                                    const float* __restrict__ G,
+                                                    float* __restrict__ dq, float* __restrict__ dt,
+                                                    float* __restrict__ dx, float* __restrict__ dst,
+                                                    float* __restrict__ dsx) {
+    constexpr int CH = 16;   // ticks per register chunk
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n;
+         d += (int64_t)gridDim.x * blockDim.x) {
+        float aq = 0.f, at = 0.f, ast = 0.f, ax = 0.f, asx = 0.f;
+        const float q = Q[d], t = Tm[d], x = X[d], st = ST[d], sx = SX[d];
+        if (depo_finite(q, t, x, st, sx)) {
+            const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+            const Window wx = wt.n ? axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows)
+                                   : Window{0, 0, false};
+            for (int b0 = 0; b0 < wt.n && wx.n; b0 += CH) {
+                float w[CH], wm[CH], ws[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    w[i] = wm[i] = ws[i] = 0.f;
+                    if (b0 + i < wt.n) weight_grads(t, st, A.org_t, A.wd_t, wt, b0 + i, w[i], wm[i], ws[i]);
+                }
+                for (int a = 0; a < wx.n; ++a) {
+                    float vx, vxm, vxs;
+                    weight_grads(x, sx, A.org_x, A.wd_x, wx, a, vx, vxm, vxs);
+                    const float* g = G + (int64_t)(wx.lo + a) * A.ld + wt.lo + b0;
+                    float r = 0.f, sm = 0.f, ss = 0.f;
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) {
+                        if (b0 + i < wt.n) {
+                            const float gi = g[i];
+                            r += gi * w[i];
+                            sm += gi * wm[i];
+                            ss += gi * ws[i];
+                        }
+                    }
+                    aq += vx * r;
+                    at += vx * sm;
+                    ast += vx * ss;
+                    ax += vxm * r;
+                    asx += vxs * r;
+                }
+            }
+        }
+        dq[d] = aq;
+        dt[d] = q * at;
+        dst[d] = q * ast;
+        dx[d] = q * ax;
+        dsx[d] = q * asx;
+    }
+}
+
+hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
+                             const float* st, const float* sx, int64_t n, const float* grid_grad,
+                             float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256, cap = 16 * (int64_t)device_cus();
+    hipLaunchKernelGGL(k_raster_bwd, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, s, a,
+                       q, t, x, st, sx, n, grid_grad, dq, dt, dx, dst, dsx);
+    return hipGetLastError();
 }
 
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,

@@ -59,6 +59,10 @@ SIGNATURES = {
                                         ctypes.c_int),
     "lar_response_spectrum": ([_P(lar_plane), _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _SZ, _VP],
                               ctypes.c_int),
+    "lar_fftconv_backward_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_fftconv_backward": ([_P(lar_plane), _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
+    "lar_raster_backward": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
+                            ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_sample_counts": ([ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.c_uint64,
                            _VP, _VP], ctypes.c_int),
@@ -191,6 +195,29 @@ def sim_plane(plane, depos: DeviceDepos, nsigma, fluct, resp, wave, ws, stream=N
     ds = depos.struct()
     _check(_lib().lar_sim_plane(ctypes.byref(pl), ctypes.byref(ds), float(nsigma), _fluct(fluct), _ptr(resp),
                                 _ptr(wave), _ptr(ws), ws.numel(), _stream(stream)), "lar_sim_plane")
+
+
+def fftconv_backward_workspace(plane) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_fftconv_backward_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)),
+           "lar_fftconv_backward_workspace")
+    return n.value
+
+
+def fftconv_backward(plane, grid, resp, wave_grad, grid_grad, resp_grad, ws, stream=None):
+    pl = make_plane(plane)
+    _check(_lib().lar_fftconv_backward(ctypes.byref(pl), _ptr(grid), _ptr(resp), _ptr(wave_grad),
+                                       _ptr(grid_grad), _ptr(resp_grad), _ptr(ws), ws.numel(),
+                                       _stream(stream)), "lar_fftconv_backward")
+
+
+def raster_backward(plane, depos: DeviceDepos, nsigma, grid_grad, dq, dt, dx, dsigma_t, dsigma_x,
+                    stream=None):
+    pl = make_plane(plane)
+    ds = depos.struct()
+    _check(_lib().lar_raster_backward(ctypes.byref(pl), ctypes.byref(ds), float(nsigma), _ptr(grid_grad),
+                                      _ptr(dq), _ptr(dt), _ptr(dx), _ptr(dsigma_t), _ptr(dsigma_x),
+                                      _stream(stream)), "lar_raster_backward")
 
 
 def response_spectrum_workspace(plane, half_w, n_rt) -> int:

@@ -1,0 +1,186 @@
+"""GPU gradients against the FP64 oracle gradient and FP64 central finite
+differences.  Tolerance: relative L2 <= 1e-4 on every gradient array."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_02479_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL_GRAD = 1e-4
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _t():
+    import torch
+    from paper_2203_02479_amd import lar
+    return torch, lar
+
+
+@pytest.mark.parametrize("case", [dict(n_wires=5, n_ticks=40, n_imp=2, nt_fft=48, nw_fft=9),
+                                  dict(n_wires=64, n_ticks=1024, n_imp=10, nt_fft=1024, nw_fft=96),
+                                  dict(n_wires=30, n_ticks=6000, n_imp=10, nt_fft=6144, nw_fft=512)])
+def test_fftconv_backward_vs_oracle(case):
+    torch, lar = _t()
+    P = inputs.Plane(**case)
+    S = inputs.random_grid(P, 1, density=0.3)
+    R = inputs.random_spectrum(P, 2)
+    G = np.random.default_rng(3).standard_normal((P.n_wires, P.n_ticks)).astype(np.float32)
+    cu = lambda a: torch.as_tensor(a).cuda().contiguous()
+    gg = torch.full((P.n_rows, P.n_ticks), float("nan"), device="cuda")
+    rg = torch.ones(R.shape, device="cuda")          # accumulates onto ones
+    ws = lar.workspace(lar.fftconv_backward_workspace(P))
+    lar.fftconv_backward(P, cu(S), cu(R), cu(G), gg, rg, ws)
+    torch.cuda.synchronize()
+    GS, dR = oracle.conv_adjoint(P, S, R, G)
+    assert rel_l2(gg.cpu().numpy(), GS) < RTOL_GRAD
+    got = rg.cpu().numpy() - 1.0
+    assert rel_l2(got[..., 0] + 1j * got[..., 1], dR) < RTOL_GRAD
+    # grid gradient alone, no grid needed
+    gg2 = torch.zeros_like(gg)
+    lar.fftconv_backward(P, None, cu(R), cu(G), gg2, None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(gg2, gg)
+
+
+@pytest.mark.parametrize("kind", ["cfg0", "random"])
+def test_raster_backward_vs_oracle(kind):
+    torch, lar = _t()
+    if kind == "cfg0":
+        ev = inputs.cfg0_event()
+        P, dep = ev.planes[0], ev.depos[0]
+    else:
+        P = inputs.Plane(n_wires=20, n_ticks=300, n_imp=10)
+        dep = inputs.random_depos(P, 3000, 4, sigma_scale=3.0, margin=0.2)
+        dep.sigma_t[:20] = 0.0                        # point axes
+    G = np.random.default_rng(5).standard_normal((P.n_rows, P.n_ticks)).astype(np.float32)
+    D = lar.DeviceDepos.from_host(dep)
+    outs = [torch.full((len(dep),), float("nan"), device="cuda") for _ in range(5)]
+    lar.raster_backward(P, D, 3.0, torch.as_tensor(G).cuda(), *outs)
+    torch.cuda.synchronize()
+    ref = oracle.raster_adjoint(P, dep, 3.0, G)
+    for name, o, r in zip(("q", "t", "x", "sigma_t", "sigma_x"), outs, ref):
+        assert rel_l2(o.cpu().numpy(), r) < RTOL_GRAD, name
+
+
+def _loss_setup(ev, scale_sigma=1.1, scale_resp=0.95):
+    P, dep = ev.planes[0], ev.depos[0]
+    r = inputs.response_time(P.n_imp, P.half_w, 200, P.kind)
+    R = oracle.response_spectrum(P, r)
+    tgt_dep = inputs.Depos(dep.q, dep.t, dep.x, (dep.sigma_t * scale_sigma).astype(np.float32),
+                           (dep.sigma_x * scale_sigma).astype(np.float32))
+    T = oracle.sim_plane_mean(P, tgt_dep, R * scale_resp)
+    R32 = np.stack([R.real, R.imag], -1).astype(np.float32)
+    return P, dep, R32, T
+
+
+def _oracle_grads(P, dep, R32, T):
+    Rc = oracle.resp_complex(R32)
+    S = oracle.raster_mean(P, dep)
+    M = oracle.conv_fft(P, S, Rc)
+    N = M.size
+    L = np.mean((M - T) ** 2)
+    G = 2.0 * (M - T) / N
+    GS, dR = oracle.conv_adjoint(P, S, Rc, G)
+    return L, oracle.raster_adjoint(P, dep, 3.0, GS), dR
+
+
+def _gpu_grads(P, dep, R32, T):
+    torch, lar = _t()
+    from paper_2203_02479_amd.autograd import sim_plane
+    arrs = [torch.as_tensor(a).cuda().requires_grad_(True) for a in dep.arrays()]
+    resp = torch.as_tensor(R32).cuda().requires_grad_(True)
+    M = sim_plane(*arrs, resp, P, 3.0)
+    L = torch.mean((M.double() - torch.as_tensor(T).cuda()) ** 2)
+    L.backward()
+    return float(L), [a.grad.cpu().numpy() for a in arrs], resp.grad.cpu().numpy()
+
+
+def test_autograd_matches_oracle_gradient_200k():
+    """Loss = MSE against waveforms of the oracle with sigmas x1.1 and the
+    response x0.95, on the 480-wire plane with 200k track depos."""
+    ev = inputs.cfg4_events(n_events=1)[0]
+    P, dep, R32, T = _loss_setup(ev)
+    L0, gdep, gR = _oracle_grads(P, dep, R32, T)
+    L1, hdep, hR = _gpu_grads(P, dep, R32, T)
+    assert L1 == pytest.approx(L0, rel=1e-4)
+    for name, h, g in zip(("q", "t", "x", "sigma_t", "sigma_x"), hdep, gdep):
+        assert rel_l2(h, g) < RTOL_GRAD, name
+    assert rel_l2(hR[..., 0] + 1j * hR[..., 1], gR) < RTOL_GRAD
+
+
+def test_autograd_vs_central_differences():
+    """FP64 central differences of the oracle loss at 100 random parameters
+    (depo fields and response-spectrum bins), step 1e-6 relative to the
+    parameter's scale; windows held fixed (a parameter whose step moves a
+    window edge is re-drawn)."""
+    ev = inputs.cfg0_event()
+    P, dep, R32, T = _loss_setup(ev)
+    _, hdep, hR = _gpu_grads(P, dep, R32, T)
+    Rc0 = oracle.resp_complex(R32)
+
+    def loss(dep_, Rc):
+        M = oracle.conv_fft(P, oracle.raster_mean(P, dep_), Rc)
+        return np.mean((M - T) ** 2)
+
+    rng = np.random.default_rng(11)
+    arrays = [a.astype(np.float64) for a in dep.arrays()]
+    d_ = float(np.float32(P.pitch)) / P.n_imp
+    scales = [np.abs(arrays[0]), arrays[3], arrays[4], arrays[3], arrays[4]]
+
+    def win(par):
+        lo_t, wt, _, _ = oracle.axis(par[1], par[3], 3.0, 0.0, float(P.tick), P.n_ticks)
+        lo_x, wx, _, _ = oracle.axis(par[2], par[4], 3.0, 0.0, d_, P.n_rows)
+        return lo_t, len(wt), lo_x, len(wx)
+
+    # the oracle's C raster takes float32 inputs, so depo FD uses a local FP64 patch
+    def depo_loss_delta(i, pi, h):
+        par = [a[i] for a in arrays]
+        lo = list(par); lo[pi] -= h
+        hi = list(par); hi[pi] += h
+        if win(lo) != win(par) or win(hi) != win(par):
+            return None
+        def patch(pp):
+            lo_t, wt, _, _ = oracle.axis(pp[1], pp[3], 3.0, 0.0, float(P.tick), P.n_ticks)
+            lo_x, wx, _, _ = oracle.axis(pp[2], pp[4], 3.0, 0.0, d_, P.n_rows)
+            Sg = np.zeros((P.n_rows, P.n_ticks))
+            Sg[lo_x:lo_x + len(wx), lo_t:lo_t + len(wt)] = pp[0] * np.outer(wx, wt)
+            return Sg
+        dM_hi = oracle.conv_fft(P, patch(hi) - patch(par), Rc0)
+        dM_lo = oracle.conv_fft(P, patch(lo) - patch(par), Rc0)
+        return np.mean((M0 + dM_hi - T) ** 2) - np.mean((M0 + dM_lo - T) ** 2)
+
+    M0 = oracle.conv_fft(P, oracle.raster_mean(P, dep), Rc0)
+    checked = 0
+    tries = 0
+    g_scale = [np.sqrt(np.mean(h.astype(np.float64) ** 2)) for h in hdep]
+    while checked < 80 and tries < 400:
+        tries += 1
+        pi, i = int(rng.integers(0, 5)), int(rng.integers(0, len(dep)))
+        h = 1e-6 * max(float(scales[pi][i]), 1e-3)
+        dl = depo_loss_delta(i, pi, h)
+        if dl is None:
+            continue
+        fd = dl / (2 * h)
+        got = float(hdep[pi][i])
+        assert abs(got - fd) <= 2e-3 * abs(fd) + 1e-3 * g_scale[pi], (pi, i, got, fd)
+        checked += 1
+    assert checked >= 60
+    # response-spectrum bins: L is quadratic in R, central differences are exact up to rounding
+    hR_c = hR[..., 0].astype(np.float64), hR[..., 1].astype(np.float64)
+    gsc = np.sqrt(np.mean(hR_c[0] ** 2 + hR_c[1] ** 2))
+    for _ in range(20):
+        k, p_, f = (int(rng.integers(0, s)) for s in Rc0.shape)
+        for part in (0, 1):
+            E = np.zeros_like(Rc0)
+            h = 1e-6 * max(abs(Rc0[k, p_, f]), 1.0)
+            E[k, p_, f] = h if part == 0 else 1j * h
+            fd = (loss(dep, Rc0 + E) - loss(dep, Rc0 - E)) / (2 * h)
+            got = hR_c[part][k, p_, f]
+            assert abs(got - fd) <= 2e-3 * abs(fd) + 1e-3 * gsc, (k, p_, f, part, got, fd)
