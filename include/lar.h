@@ -176,6 +176,46 @@ int lar_sample_counts(int32_t mode, int64_t n, const float *q, const double *p,
                       const uint32_t *ctr3, uint32_t plane, uint64_t seed, float *out,
                       void *stream);
 
+/* ---------------------------------------------------------------- batching
+ * Many (event, plane) items in one launch sequence (no paper counterpart:
+ * the paper raises throughput by running independent processes per GPU,
+ * Sec. 3.3).  One persistent raster launch covers every item's depos; each
+ * plane type then takes one launch per FFT stage for all of its items, with
+ * the response spectrum shared.  Each item's waveforms equal those of
+ * lar_sim_plane on the same depos with fluct {mode, event, plane, seed}
+ * (fluctuated counts exactly; mean grids up to float summation order). */
+typedef struct lar_batch_item {
+    int32_t plane_type;     /* index into planes[] and resp[] */
+    uint32_t event;         /* fluctuation counter words of this item */
+    uint32_t plane;         /* < 256 */
+    int32_t reserved;
+    int64_t depo_offset;    /* first depo of the item in the concatenated arrays */
+    int64_t n_depos;
+    int64_t wave_offset;    /* first float of the item's [n_wires][n_ticks] waveforms */
+} lar_batch_item;
+
+typedef struct lar_batch lar_batch;    /* opaque plan */
+
+/* Workspace for a plan: item and row tables, every item's grid, time
+ * spectra and wire-pass output, and the raster queue (fluct only). */
+int lar_batch_workspace(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
+                        int32_t n_items, const lar_fluct *fluct, size_t *bytes);
+
+/* Build a plan for these exact device buffers: depos holds all items'
+ * depos (concatenated), resp[t] the spectrum of plane type t, wave the
+ * output.  Uploads the tables to the workspace (a synchronous copy) and,
+ * with use_graph, captures the whole sequence into a hipGraph.  The
+ * contents of depos / resp may change between runs; their addresses and
+ * the item counts may not.  Setup call: it allocates host memory and the
+ * graph. */
+int lar_batch_create(const lar_plane *planes, int32_t n_types, const float *const *resp,
+                     const lar_depos *depos, float nsigma, const lar_fluct *fluct,
+                     const lar_batch_item *items, int32_t n_items, float *wave, void *workspace,
+                     size_t ws_bytes, int32_t use_graph, lar_batch **plan);
+/* Run the plan on `stream` (one graph launch with use_graph). */
+int lar_batch_run(lar_batch *plan, void *stream);
+int lar_batch_destroy(lar_batch *plan);
+
 /* Profiling aid (no paper counterpart): when events is non-NULL, the calls
  * on this host thread record events[i] (each a hipEvent_t created by the
  * caller) on their stream right after kernel stage i: 0 grid clear,

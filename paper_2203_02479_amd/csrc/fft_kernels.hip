@@ -139,7 +139,8 @@ template <int VPT, int NT>
 __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                                                           int64_t ld_in, int nrows, FftPlan plan,
                                                           float* __restrict__ out, int64_t ld_out,
-                                                          int n_out, float scale, int pairs_ok) {
+                                                          int n_out, float scale, int pairs_ok,
+                                                          const int64_t* __restrict__ row_off) {
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = blockDim.x;
     float2* A = lds;
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
             load_spec_pairs<VH>(in + (int64_t)(row + gridDim.x) * ld_in, Nh, tid, T, xa, xb);
         lds_barrier();
         fft_lds<VPT, 1>(A, plan, tid, T, tw, true);
-        float* y = out + (int64_t)row * ld_out;
+        float* y = out + (row_off ? row_off[row] : (int64_t)row * ld_out);
         if (pairs_ok) {
             float2* y2 = reinterpret_cast<float2*>(y);
             const int full = n_out >> 1;
@@ -232,20 +233,23 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
 }
 
 hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
-                           int64_t ld_out, int n_out, float scale, hipStream_t s) {
+                           int64_t ld_out, int n_out, float scale, hipStream_t s,
+                           const int64_t* row_off, bool row_off_even) {
     FftPlan plan;
     if (!make_plan(nt_fft / 2, &plan)) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
     const int Nh = plan.n;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
-    const int pairs_ok =
-        ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0) ? 1 : 0;
+    const int pairs_ok = ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0 &&
+                          (row_off == nullptr || row_off_even))
+                             ? 1
+                             : 0;
     dim3 grid(row_grid(nrows));
 #define LAR_C2R(V, T)                                                                          \
     {                                                                                          \
         set_lds(k_c2r_rows<V, T>, lds);                                                        \
         hipLaunchKernelGGL((k_c2r_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, nrows, plan,  \
-                           out, ld_out, n_out, scale, pairs_ok);                               \
+                           out, ld_out, n_out, scale, pairs_ok, row_off);                      \
     }
     if (Nh <= 1024) LAR_C2R(4, 256)
     else if (Nh <= 4096) LAR_C2R(8, 512)
@@ -270,8 +274,12 @@ __device__ __forceinline__ void fill_full_table(float2* t, int n, int tid, int T
 template <int VPT, int C, int NT>
 __global__ __launch_bounds__(NT) void k_wire_fused(
     const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
-    const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM) {
+    const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
+    int64_t strideM) {
     extern __shared__ float2 lds[];
+    // blockIdx.y: item of a batch sharing this plane shape and response
+    S += (int64_t)blockIdx.y * strideS;
+    M += (int64_t)blockIdx.y * strideM;
     const int Wf = plan.n, tid = threadIdx.x, T = blockDim.x;
     float2* A = lds;               // [Wf][C]
     float2* tw = lds + Wf * C;     // [Wf]
@@ -347,12 +355,12 @@ __global__ __launch_bounds__(NT) void k_wire_fused(
 template <int VPT, int C, int NT>
 static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                               const FftPlan& plan, const float2* R, float2* M, int64_t ldM,
-                              hipStream_t s) {
+                              int batch, int64_t strideS, int64_t strideM, hipStream_t s) {
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     set_lds(k_wire_fused<VPT, C, NT>, lds);
-    dim3 grid((F + C - 1) / C), block(NT);
+    dim3 grid((F + C - 1) / C, batch), block(NT);
     hipLaunchKernelGGL((k_wire_fused<VPT, C, NT>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
-                       plan, R, M, ldM);
+                       plan, R, M, ldM, strideS, strideM);
     return hipGetLastError();
 }
 
@@ -360,14 +368,18 @@ static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_i
 // tiles run on one XCD and share its L2 lines) by 512 threads, so that a
 // thread holds at most 8 (16 for Wf > 512) values per tile array.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
-                             int F, const float2* R, float2* M, int64_t ldM, hipStream_t s) {
+                             int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
+                             int batch, int64_t strideS, int64_t strideM) {
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
-    if (F <= 0) return hipSuccess;
-    if (nw_fft <= 128) return wire_launch<2, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft <= 256) return wire_launch<4, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft <= 512) return wire_launch<8, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
-    if (nw_fft <= 1024) return wire_launch<16, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, s);
+    if (F <= 0 || batch <= 0) return hipSuccess;
+#define LAR_WIRE(V) \
+    return wire_launch<V, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
+    if (nw_fft <= 128) LAR_WIRE(2)
+    if (nw_fft <= 256) LAR_WIRE(4)
+    if (nw_fft <= 512) LAR_WIRE(8)
+    if (nw_fft <= 1024) LAR_WIRE(16)
+#undef LAR_WIRE
     return hipErrorInvalidValue;
 }
 

@@ -172,10 +172,15 @@ int device_cus();   // compute units of the current device (cached)
 
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
                            float2* out, int64_t ld_out, hipStream_t s);
+// row_off (device, optional): output offset of each row (else row * ld_out);
+// the even-pair stores then need every offset even.
 hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
-                           int64_t ld_out, int n_out, float scale, hipStream_t s);
+                           int64_t ld_out, int n_out, float scale, hipStream_t s,
+                           const int64_t* row_off = nullptr, bool row_off_even = false);
+// batch > 1: items at S + y * strideS -> M + y * strideM sharing R.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
-                             int F, const float2* R, float2* M, int64_t ldM, hipStream_t s);
+                             int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
+                             int batch = 1, int64_t strideS = 0, int64_t strideM = 0);
 hipError_t launch_wire_spectrum(const float2* rows, int64_t ld_rows, int n_imp, int nrw,
                                 int half_w, int nw_fft, int F, float2* resp, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, hipStream_t s);
@@ -188,15 +193,32 @@ struct RasterArgs {
     uint32_t event, plane;
     uint64_t seed;
 };
-// Fluctuated rasters need a workspace: raster_ws_fixed(n) bytes of header
-// and sub-chunk flags, then a queue of 16-byte deferred bins (capacity =
-// the remaining bytes / 16; any capacity, zero included, gives the same
-// result).  The mean raster needs none.
+// One raster work item: a depo set rasterized into one plane grid.
+// sub_begin is the global index of its first sub-chunk when several items
+// are rasterized by one launch (items sorted by sub_begin).
+struct RasterItem {
+    RasterArgs A;
+    const float *q, *t, *x, *st, *sx;
+    float* grid;
+    int64_t n;
+    int64_t sub_begin;
+};
+
+// Fluctuated rasters need a workspace: raster_ws_fixed_subs(total
+// sub-chunks) bytes of header and sub-chunk flags, then a queue of
+// kDeferredBytes-byte deferred bins (capacity = the remaining bytes /
+// kDeferredBytes; any capacity, zero included, gives the same result).  The
+// mean raster needs none.
+int64_t raster_subchunks(int64_t n);
+size_t raster_ws_fixed_subs(int64_t nsub);
 size_t raster_ws_fixed(int64_t n);
-constexpr size_t kDeferredBytes = 16;
+constexpr size_t kDeferredBytes = 24;
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,
                          size_t ws_bytes, hipStream_t s);
+// items: device table (n_items entries) or nullptr with `one` used alone.
+hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
+                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);

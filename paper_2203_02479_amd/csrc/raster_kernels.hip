@@ -580,10 +580,12 @@ static constexpr int kWaveTile = 1024;    // floats of a wave's private tile
 static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
 static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
-// Deferred bin: depo index, impact row, tick, bin probability (float).
+// Deferred bin: item, depo index within the item, impact row, tick, bin
+// probability (float).
 struct DeferredBin {
-    uint32_t depo, m, j;
+    uint32_t item, depo, m, j;
     float p;
+    uint32_t pad;
 };
 
 // Workspace of a fluctuated raster: header, one flag byte per sub-chunk,
@@ -592,9 +594,22 @@ struct RasterWs {
     unsigned long long count;    // bins queued (may exceed the capacity)
 };
 
-size_t raster_ws_fixed(int64_t n) {
-    const int64_t nsub = (n + kSub - 1) / kSub;
-    return 256 + (((size_t)nsub + 255) / 256) * 256;
+int64_t raster_subchunks(int64_t n) { return (n + kSub - 1) / kSub; }
+
+size_t raster_ws_fixed_subs(int64_t nsub) { return 256 + (((size_t)nsub + 255) / 256) * 256; }
+
+size_t raster_ws_fixed(int64_t n) { return raster_ws_fixed_subs(raster_subchunks(n)); }
+
+// The item owning global sub-chunk g: the one given by value when there is
+// no table, else a binary search over the items' first sub-chunks.
+__device__ __forceinline__ int item_of(const RasterItem* items, int n_items, int64_t g) {
+    if (!items) return 0;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].sub_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 __device__ __forceinline__ bool depo_finite(float a, float b, float c, float d, float e) {
@@ -619,16 +634,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const float* __restrict__ Q,
-                                                           const float* __restrict__ Tm,
-                                                           const float* __restrict__ X,
-                                                           const float* __restrict__ ST,
-                                                           const float* __restrict__ SX, int64_t n,
-                                                           float* __restrict__ grid,
-                                                           RasterWs* __restrict__ ws,
-                                                           uint8_t* __restrict__ flags,
-                                                           DeferredBin* __restrict__ queue,
-                                                           unsigned long long cap) {
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items, int64_t total_sub,
+              RasterWs* __restrict__ ws, uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue,
+              unsigned long long cap) {
     constexpr bool FLUCT = MODE != 0;
     __shared__ float s_w[kWaves][kSub * kSlot];
     __shared__ float s_tile[kWaves][kWaveTile];
@@ -653,10 +662,19 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
         __syncthreads();
     }
 
-    const int64_t nsub = (n + kSub - 1) / kSub;
-    for (int64_t sub = (int64_t)blockIdx.x * kWaves + wv; sub < nsub;
-         sub += (int64_t)gridDim.x * kWaves) {
-        const int64_t base = sub * kSub;
+    for (int64_t gsub = (int64_t)blockIdx.x * kWaves + wv; gsub < total_sub;
+         gsub += (int64_t)gridDim.x * kWaves) {
+        const int it = item_of(items, n_items, gsub);
+        const RasterItem& I = items ? items[it] : one;
+        const RasterArgs& A = I.A;
+        const float* __restrict__ Q = I.q;
+        const float* __restrict__ Tm = I.t;
+        const float* __restrict__ X = I.x;
+        const float* __restrict__ ST = I.st;
+        const float* __restrict__ SX = I.sx;
+        float* __restrict__ grid = I.grid;
+        const int64_t n = I.n;
+        const int64_t base = (gsub - I.sub_begin) * kSub;
         // ---- windows: lane d < kSub takes depo base + d
         int nt = 0, nx = 0, jlo = 0, mlo = 0, cells = 0;
         int bj0 = INT_MAX, bj1 = INT_MIN, bm0 = INT_MAX, bm1 = INT_MIN;
@@ -833,6 +851,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
                                 const unsigned long long slot = gb + (unsigned long long)e;
                                 if (slot >= cap) continue;
                                 DeferredBin db;
+                                db.item = (uint32_t)it;
+                                db.pad = 0u;
                                 if (fits) {
                                     const int cd = s_queue[wv][e];
                                     const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
@@ -846,7 +866,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster(RasterArgs A, const f
                                 }
                                 queue[slot] = db;
                             }
-                            if (!fits && lane == 0) flags[sub] = 1;
+                            if (!fits && lane == 0) flags[gsub] = 1;
                             nq = 0;
                             wave_lds_sync();
                         }
@@ -879,8 +899,7 @@ __global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
 // The queued bins with the full rejection samplers (skipping bins of
 // sub-chunks left to k_raster_overflow).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_raster_deferred(RasterArgs A, const float* __restrict__ Q,
-                                                         float* __restrict__ grid,
+__global__ __launch_bounds__(256) void k_raster_deferred(RasterItem one, const RasterItem* __restrict__ items,
                                                          const RasterWs* __restrict__ ws,
                                                          const uint8_t* __restrict__ flags,
                                                          const DeferredBin* __restrict__ queue,
@@ -889,31 +908,32 @@ __global__ __launch_bounds__(256) void k_raster_deferred(RasterArgs A, const flo
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
          i += (unsigned long long)gridDim.x * blockDim.x) {
         const DeferredBin db = queue[i];
-        if (db.depo == kInvalid || flags[db.depo / kSub]) continue;
+        if (db.depo == kInvalid) continue;
+        const RasterItem& I = items ? items[db.item] : one;
+        if (flags[I.sub_begin + db.depo / kSub]) continue;
+        const RasterArgs& A = I.A;
         const uint32_t bin = (uint32_t)((int64_t)db.m * A.n_ticks + db.j);
-        const float v = bin_count_in<true>(MODE, Q[db.depo], (double)db.p, A.seed, db.depo, A.event,
+        const float v = bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo, A.event,
                                            bin, A.plane);
-        if (v != 0.f) atomicAdd(&grid[(int64_t)db.m * A.ld + db.j], v);
+        if (v != 0.f) atomicAdd(&I.grid[(int64_t)db.m * A.ld + db.j], v);
     }
 }
 
 // Sub-chunks whose deferred bins did not fit in the queue: recompute their
 // regular depos' bins and draw the deferred ones with the full samplers.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_raster_overflow(RasterArgs A, const float* __restrict__ Q,
-                                                         const float* __restrict__ Tm,
-                                                         const float* __restrict__ X,
-                                                         const float* __restrict__ ST,
-                                                         const float* __restrict__ SX, int64_t n,
-                                                         float* __restrict__ grid,
+__global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const RasterItem* __restrict__ items,
+                                                         int n_items, int64_t total_sub,
                                                          const uint8_t* __restrict__ flags) {
-    const int64_t nsub = (n + kSub - 1) / kSub;
-    for (int64_t sub = blockIdx.x; sub < nsub; sub += gridDim.x) {
-        if (!flags[sub]) continue;
+    for (int64_t gsub = blockIdx.x; gsub < total_sub; gsub += gridDim.x) {
+        if (!flags[gsub]) continue;
+        const RasterItem& I = items ? items[item_of(items, n_items, gsub)] : one;
+        const RasterArgs& A = I.A;
+        const int64_t sub = gsub - I.sub_begin;
         for (int dd = 0; dd < kSub; ++dd) {
             const int64_t gd = sub * kSub + dd;
-            if (gd >= n) break;
-            const float q = Q[gd], t = Tm[gd], x = X[gd], st = ST[gd], sx = SX[gd];
+            if (gd >= I.n) break;
+            const float q = I.q[gd], t = I.t[gd], x = I.x[gd], st = I.st[gd], sx = I.sx[gd];
             if (!depo_finite(q, t, x, st, sx)) continue;
             const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
             if (!wt.n) continue;
@@ -930,7 +950,7 @@ __global__ __launch_bounds__(256) void k_raster_overflow(RasterArgs A, const flo
                 float v = bin_count_fast<MODE>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                 if (v != v) {
                     v = bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                    if (v != 0.f) atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                    if (v != 0.f) atomicAdd(&I.grid[(int64_t)m * A.ld + j], v);
                 }
             }
         }
@@ -938,54 +958,61 @@ __global__ __launch_bounds__(256) void k_raster_overflow(RasterArgs A, const flo
 }
 
 // Depos whose window exceeds the weight slots of k_raster (kMaxT ticks or
-// kMaxX impact rows): each workgroup scans a chunk of depos, and processes
-// the wide ones cooperatively, one cell per thread, weights per cell.
+// kMaxX impact rows): a workgroup scans kRasterThreads / kSub sub-chunks,
+// one depo slot per thread, and processes the wide depos cooperatively, one
+// cell per thread with weights per cell.
 template <int MODE>
-__global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterArgs A, const float* __restrict__ Q,
-                                                                const float* __restrict__ Tm,
-                                                                const float* __restrict__ X,
-                                                                const float* __restrict__ ST,
-                                                                const float* __restrict__ SX, int64_t n,
-                                                                float* __restrict__ grid) {
+__global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterItem one,
+                                                                const RasterItem* __restrict__ items,
+                                                                int n_items, int64_t total_sub) {
     __shared__ int s_list[kRasterThreads];
     __shared__ int s_n;
+    constexpr int SUBS = kRasterThreads / kSub;
     const int tid = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * kRasterThreads; base < n;
-         base += (int64_t)gridDim.x * kRasterThreads) {
+    for (int64_t g0 = (int64_t)blockIdx.x * SUBS; g0 < total_sub; g0 += (int64_t)gridDim.x * SUBS) {
         if (tid == 0) s_n = 0;
         __syncthreads();
-        int64_t d = base + tid;
-        if (d < n) {
-            float q = Q[d], t = Tm[d], x = X[d], st = ST[d], sx = SX[d];
-            if (depo_finite(q, t, x, st, sx)) {
-                Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
-                Window wx = wt.n ? axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows)
-                                 : Window{0, 0, false};
-                if (wt.n && wx.n && (wt.n > kMaxT || wx.n > kMaxX)) s_list[atomicAdd(&s_n, 1)] = tid;
+        const int64_t gsub = g0 + tid / kSub;
+        if (gsub < total_sub) {
+            const RasterItem& I = items ? items[item_of(items, n_items, gsub)] : one;
+            const RasterArgs& A = I.A;
+            const int64_t d = (gsub - I.sub_begin) * kSub + tid % kSub;
+            if (d < I.n) {
+                const float q = I.q[d], t = I.t[d], x = I.x[d], st = I.st[d], sx = I.sx[d];
+                if (depo_finite(q, t, x, st, sx)) {
+                    const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+                    const Window wx = wt.n ? axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows)
+                                           : Window{0, 0, false};
+                    if (wt.n && wx.n && (wt.n > kMaxT || wx.n > kMaxX)) s_list[atomicAdd(&s_n, 1)] = tid;
+                }
             }
         }
         __syncthreads();
         const int nw = s_n;
         for (int i = 0; i < nw; ++i) {
-            int64_t gd = base + s_list[i];
-            float q = Q[gd], t = Tm[gd], x = X[gd], st = ST[gd], sx = SX[gd];
-            Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
-            Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
-            int64_t ncell = (int64_t)wt.n * wx.n;
+            const int slot = s_list[i];
+            const int64_t gsub = g0 + slot / kSub;
+            const RasterItem& I = items ? items[item_of(items, n_items, gsub)] : one;
+            const RasterArgs& A = I.A;
+            const int64_t gd = (gsub - I.sub_begin) * kSub + slot % kSub;
+            const float q = I.q[gd], t = I.t[gd], x = I.x[gd], st = I.st[gd], sx = I.sx[gd];
+            const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+            const Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
+            const int64_t ncell = (int64_t)wt.n * wx.n;
             for (int64_t c = tid; c < ncell; c += kRasterThreads) {
-                int a = (int)(c / wt.n), b = (int)(c - (int64_t)a * wt.n);
-                float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
-                float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
-                int j = wt.lo + b, m = wx.lo + a;
+                const int a = (int)(c / wt.n), b = (int)(c - (int64_t)a * wt.n);
+                const float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
+                const float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
+                const int j = wt.lo + b, m = wx.lo + a;
                 float v;
                 if (MODE == 0) {
                     v = q * wtv * wxv;
                 } else {
-                    double p = (double)(wtv * wxv);
-                    uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                    const double p = (double)(wtv * wxv);
+                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
                     v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                 }
-                if (v != 0.f) atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                if (v != 0.f) atomicAdd(&I.grid[(int64_t)m * A.ld + j], v);
             }
         }
         __syncthreads();
@@ -1092,46 +1119,57 @@ hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t
     return hipGetLastError();
 }
 
-hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
-                         const float* st, const float* sx, int64_t n, float* grid, void* ws,
-                         size_t ws_bytes, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
+                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (total_sub <= 0) return hipSuccess;
     const int64_t cap_blocks = 8 * (int64_t)device_cus();
-    const int64_t nsub = (n + kSub - 1) / kSub;
-    const int64_t nblk = (nsub + kWaves - 1) / kWaves;
+    const int64_t nblk = (total_sub + kWaves - 1) / kWaves;
     dim3 grd((unsigned)(nblk < cap_blocks ? nblk : cap_blocks)), blk(kRasterThreads);
-    const int64_t nwide = (n + kRasterThreads - 1) / kRasterThreads;
+    const int64_t nwide = (total_sub + (kRasterThreads / kSub) - 1) / (kRasterThreads / kSub);
     dim3 gw((unsigned)(nwide < cap_blocks ? nwide : cap_blocks));
-    if (a.mode == 0) {
-        hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid, nullptr,
-                           nullptr, nullptr, 0ull);
-        hipLaunchKernelGGL(k_raster_wide<0>, gw, blk, 0, s, a, q, t, x, st, sx, n, grid);
+    if (mode == 0) {
+        hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, one, items, n_items, total_sub, nullptr, nullptr,
+                           nullptr, 0ull);
+        hipLaunchKernelGGL(k_raster_wide<0>, gw, blk, 0, s, one, items, n_items, total_sub);
         return hipGetLastError();
     }
-    const size_t fixed = raster_ws_fixed(n);
+    const size_t fixed = raster_ws_fixed_subs(total_sub);
     RasterWs* hdr = reinterpret_cast<RasterWs*>(ws);
     uint8_t* flags = reinterpret_cast<uint8_t*>(ws) + 256;
     DeferredBin* queue = reinterpret_cast<DeferredBin*>(reinterpret_cast<char*>(ws) + fixed);
     const unsigned long long cap = (unsigned long long)((ws_bytes - fixed) / sizeof(DeferredBin));
-    const int64_t rblk = (nsub + 255) / 256;
-    hipLaunchKernelGGL(k_raster_reset, dim3((unsigned)(rblk < cap_blocks ? (rblk > 0 ? rblk : 1) : cap_blocks)),
-                       dim3(256), 0, s, hdr, flags, nsub);
-    dim3 gsub((unsigned)(nsub < cap_blocks ? nsub : cap_blocks));
-#define LAR_FLUCT(M)                                                                              \
-    hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, a, q, t, x, st, sx, n, grid, hdr, flags, queue, \
-                       cap);                                                                      \
-    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(256), 0, s, a, q,    \
-                       grid, hdr, flags, queue, cap);                                             \
-    hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, a, q, t, x, st, sx, n, grid,  \
-                       flags);                                                                    \
-    hipLaunchKernelGGL(k_raster_wide<M>, gw, blk, 0, s, a, q, t, x, st, sx, n, grid);
-    if (a.mode == 1) {
+    const int64_t rblk = (total_sub + 255) / 256;
+    hipLaunchKernelGGL(k_raster_reset, dim3((unsigned)(rblk < cap_blocks ? rblk : cap_blocks)), dim3(256),
+                       0, s, hdr, flags, total_sub);
+    dim3 gsub((unsigned)(total_sub < cap_blocks ? total_sub : cap_blocks));
+#define LAR_FLUCT(M)                                                                                 \
+    hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
+                       cap);                                                                         \
+    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(256), 0, s, one, items, \
+                       hdr, flags, queue, cap);                                                      \
+    hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, one, items, n_items, total_sub,   \
+                       flags);                                                                       \
+    hipLaunchKernelGGL(k_raster_wide<M>, gw, blk, 0, s, one, items, n_items, total_sub);
+    if (mode == 1) {
         LAR_FLUCT(1)
     } else {
         LAR_FLUCT(2)
     }
 #undef LAR_FLUCT
     return hipGetLastError();
+}
+
+hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
+                         const float* st, const float* sx, int64_t n, float* grid, void* ws,
+                         size_t ws_bytes, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    RasterItem one;
+    one.A = a;
+    one.q = q; one.t = t; one.x = x; one.st = st; one.sx = sx;
+    one.grid = grid;
+    one.n = n;
+    one.sub_begin = 0;
+    return launch_raster_items(a.mode, one, nullptr, 1, raster_subchunks(n), ws, ws_bytes, s);
 }
 
 }  // namespace lar

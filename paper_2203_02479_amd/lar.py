@@ -42,6 +42,12 @@ class lar_fluct(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
 
 
+class lar_batch_item(ctypes.Structure):
+    _fields_ = [("plane_type", ctypes.c_int32), ("event", ctypes.c_uint32), ("plane", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("depo_offset", ctypes.c_int64), ("n_depos", ctypes.c_int64),
+                ("wave_offset", ctypes.c_int64)]
+
+
 # name -> (argtypes, restype); every symbol declared in include/lar.h
 _P, _VP, _SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
 SIGNATURES = {
@@ -63,6 +69,12 @@ SIGNATURES = {
     "lar_fftconv_backward": ([_P(lar_plane), _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
     "lar_raster_backward": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
                             ctypes.c_int),
+    "lar_batch_workspace": ([_P(lar_plane), ctypes.c_int32, _P(lar_batch_item), ctypes.c_int32, _P(lar_fluct),
+                             _P(_SZ)], ctypes.c_int),
+    "lar_batch_create": ([_P(lar_plane), ctypes.c_int32, _P(_VP), _P(lar_depos), ctypes.c_float, _P(lar_fluct),
+                          _P(lar_batch_item), ctypes.c_int32, _VP, _VP, _SZ, ctypes.c_int32, _P(_VP)], ctypes.c_int),
+    "lar_batch_run": ([_VP, _VP], ctypes.c_int),
+    "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_sample_counts": ([ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.c_uint64,
                            _VP, _VP], ctypes.c_int),
@@ -261,3 +273,53 @@ def set_stage_events(events):
         return
     arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
     _check(_lib().lar_set_stage_events(arr, len(events)), "lar_set_stage_events")
+
+
+# ---------------------------------------------------------------- batching
+
+def make_items(items):
+    """items: sequence of (plane_type, event, plane, depo_offset, n_depos, wave_offset)."""
+    arr = (lar_batch_item * len(items))()
+    for i, (pt, ev, pl, off, n, woff) in enumerate(items):
+        arr[i] = lar_batch_item(int(pt), int(ev), int(pl), 0, int(off), int(n), int(woff))
+    return arr
+
+
+def batch_workspace(planes, items, fluct=None) -> int:
+    pls = (lar_plane * len(planes))(*[make_plane(p) for p in planes])
+    its = make_items(items)
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_batch_workspace(pls, len(planes), its, len(its), _fluct(fluct), ctypes.byref(n)),
+           "lar_batch_workspace")
+    return n.value
+
+
+class Batch:
+    """A batch plan over fixed device buffers (depos concatenated, one
+    response spectrum per plane type, one output buffer)."""
+
+    def __init__(self, planes, resps, depos: DeviceDepos, nsigma, fluct, items, wave, ws, use_graph=True):
+        self._keep = (resps, depos, wave, ws)
+        pls = (lar_plane * len(planes))(*[make_plane(p) for p in planes])
+        rp = (ctypes.c_void_p * len(resps))(*[r.data_ptr() for r in resps])
+        its = make_items(items)
+        ds = depos.struct()
+        h = ctypes.c_void_p(0)
+        _check(_lib().lar_batch_create(pls, len(planes), rp, ctypes.byref(ds), float(nsigma), _fluct(fluct), its,
+                                       len(its), _ptr(wave), _ptr(ws), ws.numel(), 1 if use_graph else 0,
+                                       ctypes.byref(h)), "lar_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib().lar_batch_run(self._h, _stream(stream)), "lar_batch_run")
+
+    def close(self):
+        if self._h:
+            _lib().lar_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
