@@ -216,12 +216,50 @@ int lar_batch_create(const lar_plane *planes, int32_t n_types, const float *cons
 int lar_batch_run(lar_batch *plan, void *stream);
 int lar_batch_destroy(lar_batch *plan);
 
+/* ---------------------------------------------------------------- schedules
+ * Launch schedule of the FFT convolution for one plane shape (no paper
+ * counterpart: a tuning knob of this implementation).  Every valid schedule
+ * computes the same transform up to float rounding; which one is fastest
+ * depends on the shape.  Schedules are keyed by (n_wires, n_imp, n_ticks,
+ * nt_fft, nw_fft), process-wide, and read when a call launches its kernels
+ * (lar_batch_create reads them once).  Radix orders 0..3 pick the order of
+ * the radix-8/4/3/2 passes of a transform:
+ *   0: 8s (then one 4 or 2), then 3s   1: 4s, 3s, then one 2
+ *   2: 3s, then 8s (then one 4 or 2)  3: the reverse of 0 */
+typedef struct lar_schedule {
+    int32_t row_threads;    /* threads per time-axis row workgroup: 256, 512, 1024 */
+    int32_t row_order;      /* radix order of the nt_fft/2-point plan */
+    int32_t wire_cols;      /* time-frequency columns per wire-pass tile: 4, 8, 16 */
+    int32_t wire_threads;   /* threads per wire-pass workgroup: 256, 512, 1024
+                               (cols 4: 256/512; cols 16: 512/1024) */
+    int32_t wire_order;     /* radix order of the nw_fft-point plan */
+    int32_t reserved;       /* 0 */
+} lar_schedule;
+
+/* The built-in schedule of a shape / the one in effect (registered or
+ * built-in).  LAR_ESIZE if the shape has no valid FFT plan. */
+int lar_schedule_default(const lar_plane *plane, lar_schedule *out);
+int lar_schedule_get(const lar_plane *plane, lar_schedule *out);
+/* Register sched for this shape (NULL: back to the built-in one).
+ * LAR_EINVAL if a field is outside the lists above or a thread holds more
+ * than 8 values of a transform (ceil(nt_fft/2 / row_threads) > 8,
+ * ceil(nw_fft * wire_cols / wire_threads) > 8) or the wire tile exceeds the
+ * 160 KB LDS of a CU.  Thread-safe; calls that overlap a change may launch
+ * with either schedule. */
+int lar_schedule_set(const lar_plane *plane, const lar_schedule *sched);
+/* Valid schedules to time: every row choice with the built-in wire pass,
+ * then every other wire choice with the built-in rows (radix orders that
+ * repeat an earlier order's plan are left out).  Writes up to cap entries
+ * and sets *n to the full count. */
+int lar_schedule_candidates(const lar_plane *plane, lar_schedule *out, int32_t cap, int32_t *n);
+
 /* Profiling aid (no paper counterpart): when events is non-NULL, the calls
  * on this host thread record events[i] (each a hipEvent_t created by the
  * caller) on their stream right after kernel stage i: 0 grid clear,
- * 1 raster, 2 time-axis real FFT, 3 wire pass, 4 time-axis inverse real FFT
- * (lar_fftconv records 2..4, lar_raster 1).  n_events must be >= 5; pass
- * NULL to stop.  Recording adds no synchronisation. */
+ * 1 raster main kernel, 2 rest of the raster (deferred draws, overflow,
+ * wide depos), 3 time-axis real FFT, 4 wire pass, 5 time-axis inverse real
+ * FFT (lar_raster records 1-2, lar_fftconv 3-5).  n_events must be >= 6;
+ * pass NULL to stop.  Recording adds no synchronisation. */
 int lar_set_stage_events(void *const *events, int32_t n_events);
 
 #ifdef __cplusplus

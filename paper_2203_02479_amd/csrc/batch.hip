@@ -238,32 +238,35 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         const int F = p.nt_fft / 2 + 1;
         const float scale = (float)(1.0 / ((double)p.nw_fft * (double)p.nt_fft));
         const int64_t* ro = drow + type_row0[t];
+        const Sched sc = sched_for(p.n_wires, p.n_imp, p.n_ticks, p.nt_fft, p.nw_fft);
         // grids of one type are gstride apart: contiguous rows when padded to none
         if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
             b->steps.push_back([=](hipStream_t s) {
-                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s);
+                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s,
+                                       sc.row_threads, sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
                 b->steps.push_back([=](hipStream_t s) {
                     return launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft,
-                                           S + r * sstride, ld, s);
+                                           S + r * sstride, ld, s, sc.row_threads, sc.row_order);
                 });
         }
         b->steps.push_back([=](hipStream_t s) {
             return launch_wire_fused(S, ld, p.n_wires, p.n_imp, p.nw_fft, F, R, M, ld, s, k, sstride,
-                                     mstride);
+                                     mstride, sc.wire_cols, sc.wire_threads, sc.wire_order);
         });
         if (mstride == (int64_t)p.n_wires * ld) {
             b->steps.push_back([=](hipStream_t s) {
                 return launch_c2r_rows(M, ld, p.n_wires * k, p.nt_fft, wave, p.n_ticks, p.n_ticks, scale,
-                                       s, ro, even);
+                                       s, ro, even, sc.row_threads, sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
                 b->steps.push_back([=](hipStream_t s) {
                     return launch_c2r_rows(M + r * mstride, ld, p.n_wires, p.nt_fft, wave, p.n_ticks,
-                                           p.n_ticks, scale, s, ro + (int64_t)r * p.n_wires, even);
+                                           p.n_ticks, scale, s, ro + (int64_t)r * p.n_wires, even,
+                                           sc.row_threads, sc.row_order);
                 });
         }
     }
@@ -300,7 +303,7 @@ int lar_batch_run(lar_batch* b, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     if (b->exec) {
         hipError_t e = hipGraphLaunch(b->exec, s);
-        return e == hipSuccess ? LAR_OK : (hipGetLastError(), LAR_EHIP);
+        return e == hipSuccess ? LAR_OK : ((void)hipGetLastError(), LAR_EHIP);
     }
     for (auto& f : b->steps)
         if (f(s) != hipSuccess) return LAR_EHIP;

@@ -16,13 +16,34 @@
 
 namespace lar {
 
-bool make_plan(int n, FftPlan* plan) {
-    if (n < 1) return false;
-    int m = n, np = 0;
-    while (m % 4 == 0 && np < kMaxPasses) { plan->radix[np++] = 4; m /= 4; }
-    while (m % 3 == 0 && np < kMaxPasses) { plan->radix[np++] = 3; m /= 3; }
-    while (m % 2 == 0 && np < kMaxPasses) { plan->radix[np++] = 2; m /= 2; }
+bool make_plan(int n, FftPlan* plan, int order) {
+    if (n < 1 || order < 0 || order >= kPlanOrders) return false;
+    int m = n, a = 0, b = 0;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
     if (m != 1) return false;
+    int r[kMaxPasses + 8], np = 0;
+    auto twos_8 = [&]() {            // 2^a as 8s then one 4 or 2
+        int x = a;
+        while (x >= 3) { r[np++] = 8; x -= 3; }
+        if (x == 2) r[np++] = 4;
+        if (x == 1) r[np++] = 2;
+    };
+    auto threes = [&]() { for (int i = 0; i < b; ++i) r[np++] = 3; };
+    if (order == 0 || order == 3) {
+        twos_8();
+        threes();
+    } else if (order == 1) {
+        int x = a;
+        while (x >= 2) { r[np++] = 4; x -= 2; }
+        threes();
+        if (x == 1) r[np++] = 2;
+    } else {
+        threes();
+        twos_8();
+    }
+    if (np > kMaxPasses) return false;
+    for (int i = 0; i < np; ++i) plan->radix[i] = order == 3 ? r[np - 1 - i] : r[i];
     plan->n = n;
     plan->npass = np;
     return true;
@@ -84,7 +105,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
                                                           FftPlan plan, float2* __restrict__ out,
                                                           int64_t ld_out, int pairs_ok) {
     extern __shared__ float2 lds[];
-    const int Nh = plan.n, tid = threadIdx.x, T = blockDim.x;
+    const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
     float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
@@ -142,7 +163,7 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                                                           int n_out, float scale, int pairs_ok,
                                                           const int64_t* __restrict__ row_off) {
     extern __shared__ float2 lds[];
-    const int Nh = plan.n, tid = threadIdx.x, T = blockDim.x;
+    const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
     float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
@@ -206,14 +227,56 @@ static int row_grid(int nrows) {
     return nrows < g ? nrows : g;
 }
 
-// Row kernels: 256 threads for half-lengths up to 1024, 512 above, so that
-// a thread holds at most 8 (16 above 4096) values of a row.
-hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
-                           float2* out, int64_t ld_out, hipStream_t s) {
+// Values per thread of a transform of n points over T threads, rounded up to
+// the instantiated 1, 2, 4 or 8; 0 if more than 8 would be needed.
+static int vpt_for(int n, int T) {
+    const int need = (n + T - 1) / T;
+    for (int v = 1; v <= 8; v *= 2)
+        if (need <= v) return v;
+    return 0;
+}
+
+int default_row_threads(int nt_fft) {
+    const int Nh = nt_fft / 2;
+    return Nh <= 1024 ? 256 : Nh <= 4096 ? 512 : 1024;
+}
+
+bool row_sched_ok(int nt_fft, int threads, int order) {
     FftPlan plan;
-    if (!make_plan(nt_fft / 2, &plan)) return hipErrorInvalidValue;
+    return (threads == 256 || threads == 512 || threads == 1024) && vpt_for(nt_fft / 2, threads) &&
+           make_plan(nt_fft / 2, &plan, order);
+}
+
+// Instantiations: T in {256, 512, 1024} threads by V in {1, 2, 4, 8} values
+// per thread; f(V, T) is called with the pair that a schedule selects.
+#define LAR_ROW_DISPATCH(V, T, X)                                   \
+    switch ((T) * 16 + (V)) {                                       \
+        case 256 * 16 + 1: X(1, 256) break;                         \
+        case 256 * 16 + 2: X(2, 256) break;                         \
+        case 256 * 16 + 4: X(4, 256) break;                         \
+        case 256 * 16 + 8: X(8, 256) break;                         \
+        case 512 * 16 + 1: X(1, 512) break;                         \
+        case 512 * 16 + 2: X(2, 512) break;                         \
+        case 512 * 16 + 4: X(4, 512) break;                         \
+        case 512 * 16 + 8: X(8, 512) break;                         \
+        case 1024 * 16 + 1: X(1, 1024) break;                       \
+        case 1024 * 16 + 2: X(2, 1024) break;                       \
+        case 1024 * 16 + 4: X(4, 1024) break;                       \
+        case 1024 * 16 + 8: X(8, 1024) break;                       \
+        default: return hipErrorInvalidValue;                       \
+    }
+
+// Row kernels: one row per workgroup at a time, a persistent grid of
+// 4 workgroups per CU.  threads = 0 selects the default: 256 threads for
+// half-lengths up to 1024, 512 up to 4096 and 1024 above.
+hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
+                           float2* out, int64_t ld_out, hipStream_t s, int threads, int order) {
+    if (!threads) threads = default_row_threads(nt_fft);
+    FftPlan plan;
+    if (!make_plan(nt_fft / 2, &plan, order)) return hipErrorInvalidValue;
+    const int Nh = plan.n, vpt = vpt_for(Nh, threads);
+    if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const int Nh = plan.n;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
     const int pairs_ok =
         ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0) ? 1 : 0;
@@ -224,21 +287,20 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
         hipLaunchKernelGGL((k_r2c_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, n_in, nrows,   \
                            plan, out, ld_out, pairs_ok);                                        \
     }
-    if (Nh <= 1024) LAR_R2C(4, 256)
-    else if (Nh <= 4096) LAR_R2C(8, 512)
-    else if (Nh <= 8192) LAR_R2C(16, 512)
-    else return hipErrorInvalidValue;
+    LAR_ROW_DISPATCH(vpt, threads, LAR_R2C)
 #undef LAR_R2C
     return hipGetLastError();
 }
 
 hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
                            int64_t ld_out, int n_out, float scale, hipStream_t s,
-                           const int64_t* row_off, bool row_off_even) {
+                           const int64_t* row_off, bool row_off_even, int threads, int order) {
+    if (!threads) threads = default_row_threads(nt_fft);
     FftPlan plan;
-    if (!make_plan(nt_fft / 2, &plan)) return hipErrorInvalidValue;
+    if (!make_plan(nt_fft / 2, &plan, order)) return hipErrorInvalidValue;
+    const int Nh = plan.n, vpt = vpt_for(Nh, threads);
+    if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const int Nh = plan.n;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
     const int pairs_ok = ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0 &&
                           (row_off == nullptr || row_off_even))
@@ -251,10 +313,7 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
         hipLaunchKernelGGL((k_c2r_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, nrows, plan,  \
                            out, ld_out, n_out, scale, pairs_ok, row_off);                      \
     }
-    if (Nh <= 1024) LAR_C2R(4, 256)
-    else if (Nh <= 4096) LAR_C2R(8, 512)
-    else if (Nh <= 8192) LAR_C2R(16, 512)
-    else return hipErrorInvalidValue;
+    LAR_ROW_DISPATCH(vpt, threads, LAR_C2R)
 #undef LAR_C2R
     return hipGetLastError();
 }
@@ -272,7 +331,8 @@ __device__ __forceinline__ void fill_full_table(float2* t, int n, int tid, int T
 
 // One workgroup per tile of C consecutive time-frequency columns.
 template <int VPT, int C, int NT>
-__global__ __launch_bounds__(NT) void k_wire_fused(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_wire_fused(
     const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
     const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
     int64_t strideM) {
@@ -280,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_wire_fused(
     // blockIdx.y: item of a batch sharing this plane shape and response
     S += (int64_t)blockIdx.y * strideS;
     M += (int64_t)blockIdx.y * strideM;
-    const int Wf = plan.n, tid = threadIdx.x, T = blockDim.x;
+    const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;               // [Wf][C]
     float2* tw = lds + Wf * C;     // [Wf]
     fill_full_table(tw, Wf, tid, T);
@@ -293,19 +353,39 @@ __global__ __launch_bounds__(NT) void k_wire_fused(
 
     // element e = tid + i*T of the tile is (wire p = e / C, column c = e % C);
     // every gather below is unconditional (clamped address, value masked)
-    // so that a thread's VPT loads are all in flight together
-    float2 v[VPT];
+    // so that a thread's loads are all in flight together.  The next
+    // offset's grid rows are requested before this offset's FFT and its
+    // response slab right after this offset's product, so both loads
+    // overlap an FFT.
+    float2 v[VPT], r[VPT];
+    // (T is a multiple of C, so a thread's column is fixed and its wire
+    // advances by T / C per i.)  The row index passes through an empty asm
+    // so that the per-i addresses are rebuilt for each gather rather than
+    // hoisted out of the offset loop, where they would pin 2 VPT registers.
+    static_assert(NT % C == 0, "tile width must divide the thread count");
+    const int c_own = tid % C, p_own = tid / C, f_own = min(f0 + c_own, F - 1);
+    const bool f_ok = f0 + c_own < F;
     auto gather_s = [&](int k) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            int e = tid + i * T;
-            int p = e / C, f = f0 + e % C;
-            bool ok = e < nel && p < n_wires && f < F;
-            float2 x = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + min(f, F - 1)];
+            int p = p_own + i * (NT / C);
+            asm volatile("" : "+v"(p));
+            bool ok = f_ok && p < n_wires;   // n_wires <= Wf
+            float2 x = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + f_own];
             v[i] = ok ? x : make_float2(0.f, 0.f);
         }
     };
+    auto gather_r = [&](int k) {
+        const float2* Rk = R + (int64_t)k * Wf * F;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            int p = p_own + i * (NT / C);
+            asm volatile("" : "+v"(p));
+            r[i] = Rk[(int64_t)min(p, Wf - 1) * F + f_own];
+        }
+    };
     gather_s(0);
+    gather_r(0);
     for (int k = 0; k < n_imp; ++k) {
         lds_barrier();
 #pragma unroll
@@ -313,17 +393,9 @@ __global__ __launch_bounds__(NT) void k_wire_fused(
             int e = tid + i * T;
             if (e < nel) A[e] = v[i];
         }
+        if (k + 1 < n_imp) gather_s(k + 1);
         lds_barrier();
         fft_lds<VPT, C>(A, plan, tid, T, twf, false);
-        const float2* Rk = R + (int64_t)k * Wf * F;
-        float2 r[VPT];
-#pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            int e = tid + i * T;
-            int p = min(e / C, Wf - 1), f = min(f0 + e % C, F - 1);
-            r[i] = Rk[(int64_t)p * F + f];
-        }
-        if (k + 1 < n_imp) gather_s(k + 1);    // next offset's rows, in flight during the MAC
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
@@ -333,6 +405,7 @@ __global__ __launch_bounds__(NT) void k_wire_fused(
                 acc[i].y += a.x * r[i].y + a.y * r[i].x;
             }
         }
+        if (k + 1 < n_imp) gather_r(k + 1);
     }
     lds_barrier();
 #pragma unroll
@@ -364,23 +437,51 @@ static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_i
     return hipGetLastError();
 }
 
-// Tiles of 8 time-frequency columns (64-byte row segments; neighbouring
-// tiles run on one XCD and share its L2 lines) by 512 threads, so that a
-// thread holds at most 8 (16 for Wf > 512) values per tile array.
+int default_wire_threads(int nw_fft) { return nw_fft <= 512 ? 512 : 1024; }
+
+bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
+    FftPlan plan;
+    const bool shape = (cols == 4 && (threads == 256 || threads == 512)) ||
+                       (cols == 8 && (threads == 256 || threads == 512 || threads == 1024)) ||
+                       (cols == 16 && (threads == 512 || threads == 1024));
+    // the tile and its twiddle table must fit the 160 KB of LDS of a CU
+    const size_t lds = ((size_t)nw_fft * cols + nw_fft) * sizeof(float2);
+    return shape && vpt_for(nw_fft * cols, threads) && lds <= 160 * 1024 &&
+           make_plan(nw_fft, &plan, order);
+}
+
+// Tiles of C time-frequency columns (8 by default: 64-byte row segments;
+// neighbouring tiles run on one XCD and share its L2 lines) by T threads
+// (512 by default, 1024 for Wf > 512), so that a thread holds at most 8
+// values per tile array.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
                              int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
-                             int batch, int64_t strideS, int64_t strideM) {
+                             int batch, int64_t strideS, int64_t strideM, int cols, int threads,
+                             int order) {
+    if (!cols) cols = 8;
+    if (!threads) threads = default_wire_threads(nw_fft);
     FftPlan plan;
-    if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
+    if (!wire_sched_ok(nw_fft, cols, threads, order) || !make_plan(nw_fft, &plan, order))
+        return hipErrorInvalidValue;
     if (F <= 0 || batch <= 0) return hipSuccess;
-#define LAR_WIRE(V) \
-    return wire_launch<V, 8, 512>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
-    if (nw_fft <= 128) LAR_WIRE(2)
-    if (nw_fft <= 256) LAR_WIRE(4)
-    if (nw_fft <= 512) LAR_WIRE(8)
-    if (nw_fft <= 1024) LAR_WIRE(16)
-#undef LAR_WIRE
-    return hipErrorInvalidValue;
+    const int vpt = vpt_for(nw_fft * cols, threads);
+#define LAR_W(V, C, T)                                                                          \
+    case (C) * 100000 + (T) * 16 + (V):                                                         \
+        return wire_launch<V, C, T>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, \
+                                    strideM, s);
+#define LAR_W4(C, T) LAR_W(1, C, T) LAR_W(2, C, T) LAR_W(4, C, T) LAR_W(8, C, T)
+    switch (cols * 100000 + threads * 16 + vpt) {
+        LAR_W4(4, 256)
+        LAR_W4(4, 512)
+        LAR_W4(8, 256)
+        LAR_W4(8, 512)
+        LAR_W4(8, 1024)
+        LAR_W4(16, 512)
+        LAR_W4(16, 1024)
+        default: return hipErrorInvalidValue;
+    }
+#undef LAR_W4
+#undef LAR_W
 }
 
 // ---------------------------------------------------------------- wire pass, adjoint
@@ -399,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
     int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R, float2* __restrict__ dR,
     int want_grid, float resp_scale) {
     extern __shared__ float2 lds[];
-    const int Wf = plan.n, tid = threadIdx.x, T = blockDim.x;
+    const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
     float2* tw = lds + Wf * C;
     fill_full_table(tw, Wf, tid, T);
@@ -516,7 +617,9 @@ hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, float2* S, int64_t
     if (nw_fft <= 128) LAR_WADJ(2)
     if (nw_fft <= 256) LAR_WADJ(4)
     if (nw_fft <= 512) LAR_WADJ(8)
-    if (nw_fft <= 1024) LAR_WADJ(16)
+    if (nw_fft <= 1024)
+        return wire_adj_launch<8, 8, 1024>(Gt, ldG, S, ldS, n_wires, n_imp, F, nyq, plan, R, dR,
+                                           want_grid, resp_scale, s);
 #undef LAR_WADJ
     return hipErrorInvalidValue;
 }

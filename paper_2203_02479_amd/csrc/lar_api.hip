@@ -9,7 +9,7 @@
 using namespace lar;
 
 static thread_local int g_last_hip = 0;
-static thread_local hipEvent_t g_stage_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+static thread_local hipEvent_t g_stage_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
 static hipError_t stage_mark(int i, hipStream_t s) {
     return g_stage_ev[i] ? hipEventRecord(g_stage_ev[i], s) : hipSuccess;
@@ -32,6 +32,10 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Row pitch (complex elements) of the internal time-spectrum buffers: the
 // half spectrum padded to a multiple of 16 so rows start on 128-byte lines.
 static int64_t spec_ld(const lar_plane* p) { return ((int64_t)(p->nt_fft / 2 + 1) + 15) / 16 * 16; }
+
+static Sched sched_of(const lar_plane* p) {
+    return sched_for(p->n_wires, p->n_imp, p->n_ticks, p->nt_fft, p->nw_fft);
+}
 
 static bool smooth(int n) {
     if (n < 1) return false;
@@ -89,13 +93,13 @@ int lar_last_hip_error(void) { return g_last_hip; }
 
 int lar_set_stage_events(void* const* events, int32_t n_events) {
     if (!events) {
-        for (int i = 0; i < 5; ++i) g_stage_ev[i] = nullptr;
+        for (int i = 0; i < 6; ++i) g_stage_ev[i] = nullptr;
         return LAR_OK;
     }
-    if (n_events < 5) return LAR_EINVAL;
-    for (int i = 0; i < 5; ++i)
+    if (n_events < 6) return LAR_EINVAL;
+    for (int i = 0; i < 6; ++i)
         if (!events[i]) return LAR_EINVAL;
-    for (int i = 0; i < 5; ++i) g_stage_ev[i] = (hipEvent_t)events[i];
+    for (int i = 0; i < 6; ++i) g_stage_ev[i] = (hipEvent_t)events[i];
     return LAR_OK;
 }
 
@@ -139,8 +143,8 @@ static int raster_impl(const lar_plane* plane, const lar_depos* depos, float nsi
     a.plane = fluct ? fluct->plane : 0u;
     a.seed = fluct ? fluct->seed : 0ull;
     LAR_TRY(launch_raster(a, depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x,
-                          depos->n, grid, ws, ws_bytes, stream));
-    LAR_TRY(stage_mark(1, stream));
+                          depos->n, grid, ws, ws_bytes, stream, g_stage_ev[1]));
+    LAR_TRY(stage_mark(2, stream));
     return LAR_OK;
 }
 
@@ -182,14 +186,18 @@ static int fftconv_impl(const lar_plane* p, const float* grid, const float* resp
     float2* Sh = reinterpret_cast<float2*>(ws);
     float2* Mh = reinterpret_cast<float2*>(
         reinterpret_cast<char*>(ws) + align_up((size_t)rows * ld * sizeof(float2), 256));
-    LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sh, ld, s));
-    LAR_TRY(stage_mark(2, s));
-    LAR_TRY(launch_wire_fused(Sh, ld, p->n_wires, p->n_imp, p->nw_fft, F,
-                              reinterpret_cast<const float2*>(resp), Mh, ld, s));
+    const Sched sc = sched_of(p);
+    LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sh, ld, s, sc.row_threads,
+                            sc.row_order));
     LAR_TRY(stage_mark(3, s));
-    const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
-    LAR_TRY(launch_c2r_rows(Mh, ld, p->n_wires, p->nt_fft, wave, p->n_ticks, p->n_ticks, scale, s));
+    LAR_TRY(launch_wire_fused(Sh, ld, p->n_wires, p->n_imp, p->nw_fft, F,
+                              reinterpret_cast<const float2*>(resp), Mh, ld, s, 1, 0, 0,
+                              sc.wire_cols, sc.wire_threads, sc.wire_order));
     LAR_TRY(stage_mark(4, s));
+    const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
+    LAR_TRY(launch_c2r_rows(Mh, ld, p->n_wires, p->nt_fft, wave, p->n_ticks, p->n_ticks, scale, s,
+                            nullptr, false, sc.row_threads, sc.row_order));
+    LAR_TRY(stage_mark(5, s));
     return LAR_OK;
 }
 
@@ -241,6 +249,7 @@ int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
             return st;
     } else {
         LAR_TRY(stage_mark(1, s));
+        LAR_TRY(stage_mark(2, s));
     }
     return fftconv_impl(plane, grid, resp, wave, w + grid_bytes(plane), s);
 }
@@ -276,13 +285,18 @@ int lar_fftconv_backward(const lar_plane* p, const float* grid, const float* res
     float2* Sb = reinterpret_cast<float2*>(reinterpret_cast<char*>(ws) +
                                            align_up((size_t)p->n_wires * ld * sizeof(float2), 256));
     const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
-    LAR_TRY(launch_r2c_rows(wave_grad, p->n_ticks, p->n_ticks, p->n_wires, p->nt_fft, Gt, ld, s));
-    if (resp_grad) LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sb, ld, s));
+    const Sched sc = sched_of(p);
+    LAR_TRY(launch_r2c_rows(wave_grad, p->n_ticks, p->n_ticks, p->n_wires, p->nt_fft, Gt, ld, s,
+                            sc.row_threads, sc.row_order));
+    if (resp_grad)
+        LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sb, ld, s,
+                                sc.row_threads, sc.row_order));
     LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
                                 reinterpret_cast<const float2*>(resp),
                                 reinterpret_cast<float2*>(resp_grad), grid_grad != nullptr, scale, s));
     if (grid_grad)
-        LAR_TRY(launch_c2r_rows(Sb, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s));
+        LAR_TRY(launch_c2r_rows(Sb, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s,
+                                nullptr, false, sc.row_threads, sc.row_order));
     return LAR_OK;
 }
 

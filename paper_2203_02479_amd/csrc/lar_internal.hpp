@@ -16,8 +16,10 @@ namespace lar {
 // and sub-transform size Ns (product of earlier radices) reads the R inputs
 // of butterfly j at stride n/R, applies the twiddles exp(-+2 pi i r (j mod Ns)
 // / (Ns R)), and writes the R outputs at (j div Ns) Ns R + (j mod Ns) + r Ns.
-// Lengths are 2^a 3^b; passes use radix 4 first, then 3, then one 2.
+// Lengths are 2^a 3^b with passes of radix 8, 4, 3 and 2; the order of the
+// passes is a schedule choice (make_plan's `order`).
 constexpr int kMaxPasses = 16;
+constexpr int kPlanOrders = 4;
 
 struct FftPlan {
     int n;
@@ -26,7 +28,10 @@ struct FftPlan {
 };
 
 // Host: build the plan for length n; false if n is not 2^a 3^b (n >= 1).
-bool make_plan(int n, FftPlan* plan);
+// order 0: radix 8 passes first, then one 4 or 2, then the 3s; 1: radix 4
+// passes, then 3s, then one 2 (no radix 8); 2: 3s first, then 8s, then
+// 4/2; 3: the reverse of order 0.
+bool make_plan(int n, FftPlan* plan, int order = 0);
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -81,6 +86,28 @@ __device__ __forceinline__ void dft_small<4>(float2* v, bool inv) {
     v[2] = csub(a0, b0);
     v[1] = cadd(a1, mib1);
     v[3] = csub(a1, mib1);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<8>(float2* v, bool inv) {
+    // two 4-point DFTs of the even and odd samples, combined with W8^k
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<4>(e, inv);
+    dft_small<4>(o, inv);
+    const float c = 0.70710678118654752f;
+    const float sg = inv ? 1.f : -1.f;   // W8 = exp(sg i pi/4)
+    float2 w1 = cmul(o[1], make_float2(c, sg * c));
+    float2 w2 = make_float2(-sg * o[2].y, sg * o[2].x);     // * exp(sg i pi/2) = sg i
+    float2 w3 = cmul(o[3], make_float2(-c, sg * c));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], w1);
+    v[5] = csub(e[1], w1);
+    v[2] = cadd(e[2], w2);
+    v[6] = csub(e[2], w2);
+    v[3] = cadd(e[3], w3);
+    v[7] = csub(e[3], w3);
 }
 
 // Twiddle accessors: tw(m) = exp(-2 pi i m / n) for 0 <= m < n.
@@ -149,7 +176,9 @@ __device__ __forceinline__ void fft_lds(float2* A, const FftPlan& plan, int tid,
     int Ns = 1;
     for (int p = 0; p < plan.npass; ++p) {
         int R = plan.radix[p];
-        if (R == 4)
+        if (R == 8)
+            stockham_pass<8, (VPT + 7) / 8, NS>(A, plan.n, Ns, tid, T, tw, inv);
+        else if (R == 4)
             stockham_pass<4, (VPT + 3) / 4, NS>(A, plan.n, Ns, tid, T, tw, inv);
         else if (R == 3)
             stockham_pass<3, (VPT + 2) / 3, NS>(A, plan.n, Ns, tid, T, tw, inv);
@@ -170,17 +199,34 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // ---------------------------------------------------------------- launchers
 int device_cus();   // compute units of the current device (cached)
 
+// FFT-convolution launch schedule (tunable per plane shape; 0 = default):
+// threads per time-axis row workgroup and radix order of the Tf/2 plan,
+// columns and threads per wire-pass workgroup and radix order of the Wf plan.
+struct Sched {
+    int row_threads, row_order;
+    int wire_cols, wire_threads, wire_order;
+};
+int default_row_threads(int nt_fft);
+int default_wire_threads(int nw_fft);
+bool row_sched_ok(int nt_fft, int threads, int order);
+bool wire_sched_ok(int nw_fft, int cols, int threads, int order);
+// The schedule registered for this plane shape, else the default one.
+Sched sched_for(int n_wires, int n_imp, int n_ticks, int nt_fft, int nw_fft);
+
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
-                           float2* out, int64_t ld_out, hipStream_t s);
+                           float2* out, int64_t ld_out, hipStream_t s, int threads = 0,
+                           int order = 0);
 // row_off (device, optional): output offset of each row (else row * ld_out);
 // the even-pair stores then need every offset even.
 hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
                            int64_t ld_out, int n_out, float scale, hipStream_t s,
-                           const int64_t* row_off = nullptr, bool row_off_even = false);
+                           const int64_t* row_off = nullptr, bool row_off_even = false,
+                           int threads = 0, int order = 0);
 // batch > 1: items at S + y * strideS -> M + y * strideM sharing R.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
                              int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
-                             int batch = 1, int64_t strideS = 0, int64_t strideM = 0);
+                             int batch = 1, int64_t strideS = 0, int64_t strideM = 0, int cols = 0,
+                             int threads = 0, int order = 0);
 hipError_t launch_wire_spectrum(const float2* rows, int64_t ld_rows, int n_imp, int nrw,
                                 int half_w, int nw_fft, int F, float2* resp, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, hipStream_t s);
@@ -213,12 +259,14 @@ int64_t raster_subchunks(int64_t n);
 size_t raster_ws_fixed_subs(int64_t nsub);
 size_t raster_ws_fixed(int64_t n);
 constexpr size_t kDeferredBytes = 24;
+// main_done (optional): recorded on s right after the main raster kernel.
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,
-                         size_t ws_bytes, hipStream_t s);
+                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done = nullptr);
 // items: device table (n_items entries) or nullptr with `one` used alone.
 hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
-                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s);
+                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s,
+                               hipEvent_t main_done = nullptr);
 hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);

@@ -1120,7 +1120,8 @@ hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t
 }
 
 hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
-                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s) {
+                               int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s,
+                               hipEvent_t main_done) {
     if (total_sub <= 0) return hipSuccess;
     const int64_t cap_blocks = 8 * (int64_t)device_cus();
     const int64_t nblk = (total_sub + kWaves - 1) / kWaves;
@@ -1130,6 +1131,7 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     if (mode == 0) {
         hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, one, items, n_items, total_sub, nullptr, nullptr,
                            nullptr, 0ull);
+        if (main_done) (void)hipEventRecord(main_done, s);
         hipLaunchKernelGGL(k_raster_wide<0>, gw, blk, 0, s, one, items, n_items, total_sub);
         return hipGetLastError();
     }
@@ -1145,6 +1147,7 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
 #define LAR_FLUCT(M)                                                                                 \
     hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
                        cap);                                                                         \
+    if (main_done) (void)hipEventRecord(main_done, s);                                               \
     hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(256), 0, s, one, items, \
                        hdr, flags, queue, cap);                                                      \
     hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, one, items, n_items, total_sub,   \
@@ -1161,7 +1164,7 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
 
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,
-                         size_t ws_bytes, hipStream_t s) {
+                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done) {
     if (n <= 0) return hipSuccess;
     RasterItem one;
     one.A = a;
@@ -1169,7 +1172,7 @@ hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, co
     one.grid = grid;
     one.n = n;
     one.sub_begin = 0;
-    return launch_raster_items(a.mode, one, nullptr, 1, raster_subchunks(n), ws, ws_bytes, s);
+    return launch_raster_items(a.mode, one, nullptr, 1, raster_subchunks(n), ws, ws_bytes, s, main_done);
 }
 
 }  // namespace lar

@@ -48,6 +48,16 @@ class lar_batch_item(ctypes.Structure):
                 ("wave_offset", ctypes.c_int64)]
 
 
+class lar_schedule(ctypes.Structure):
+    _fields_ = [("row_threads", ctypes.c_int32), ("row_order", ctypes.c_int32), ("wire_cols", ctypes.c_int32),
+                ("wire_threads", ctypes.c_int32), ("wire_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    FIELDS = ("row_threads", "row_order", "wire_cols", "wire_threads", "wire_order")
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k in self.FIELDS}
+
+
 # name -> (argtypes, restype); every symbol declared in include/lar.h
 _P, _VP, _SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t
 SIGNATURES = {
@@ -76,6 +86,11 @@ SIGNATURES = {
     "lar_batch_run": ([_VP, _VP], ctypes.c_int),
     "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
+    "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
+    "lar_schedule_get": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
+    "lar_schedule_set": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
+    "lar_schedule_candidates": ([_P(lar_plane), _P(lar_schedule), ctypes.c_int32, _P(ctypes.c_int32)],
+                                ctypes.c_int),
     "lar_sample_counts": ([ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.c_uint64,
                            _VP, _VP], ctypes.c_int),
 }
@@ -273,6 +288,40 @@ def set_stage_events(events):
         return
     arr = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
     _check(_lib().lar_set_stage_events(arr, len(events)), "lar_set_stage_events")
+
+
+# ---------------------------------------------------------------- schedules
+
+def schedule_default(plane) -> dict:
+    out = lar_schedule()
+    _check(_lib().lar_schedule_default(ctypes.byref(make_plane(plane)), ctypes.byref(out)),
+           "lar_schedule_default")
+    return out.as_dict()
+
+
+def schedule_get(plane) -> dict:
+    out = lar_schedule()
+    _check(_lib().lar_schedule_get(ctypes.byref(make_plane(plane)), ctypes.byref(out)), "lar_schedule_get")
+    return out.as_dict()
+
+
+def schedule_set(plane, sched):
+    """Register sched (a dict with the lar_schedule fields) for this plane
+    shape; None restores the built-in schedule."""
+    ptr = None
+    if sched is not None:
+        ptr = ctypes.byref(lar_schedule(*(int(sched[k]) for k in lar_schedule.FIELDS), 0))
+    _check(_lib().lar_schedule_set(ctypes.byref(make_plane(plane)), ptr), "lar_schedule_set")
+
+
+def schedule_candidates(plane) -> list:
+    P = make_plane(plane)
+    n = ctypes.c_int32(0)
+    _check(_lib().lar_schedule_candidates(ctypes.byref(P), None, 0, ctypes.byref(n)), "lar_schedule_candidates")
+    arr = (lar_schedule * max(n.value, 1))()
+    _check(_lib().lar_schedule_candidates(ctypes.byref(P), arr, n.value, ctypes.byref(n)),
+           "lar_schedule_candidates")
+    return [arr[i].as_dict() for i in range(n.value)]
 
 
 # ---------------------------------------------------------------- batching

@@ -86,3 +86,53 @@ def test_host_side_argument_errors(lar):
     assert L.lar_fftconv(ctypes.byref(P), one, one, one, one, 16, None) == lar.LAR_EWORKSPACE
     assert L.lar_sample_counts(0, 1, one, one, one, 0, 0, one, None) == lar.LAR_EINVAL
     assert L.lar_sample_counts(1, 0, None, None, None, 0, 0, None, None) == lar.LAR_OK
+
+
+def test_schedule_registry_host_side(lar):
+    P = inputs.cfg1_plane()
+    d = lar.schedule_default(P)
+    assert d == dict(row_threads=512, row_order=0, wire_cols=8, wire_threads=512, wire_order=0)
+    assert lar.schedule_get(P) == d
+    cands = lar.schedule_candidates(P)
+    assert cands[0] == d and len(cands) == len({tuple(c.values()) for c in cands})
+    other = dict(d, wire_cols=16, wire_threads=1024, wire_order=1, row_threads=1024)
+    lar.schedule_set(P, other)
+    try:
+        assert lar.schedule_get(P) == other
+        Q = inputs.cfg1_plane()
+        Q.n_wires = 470                     # another shape keeps the built-in schedule
+        assert lar.schedule_get(Q) == lar.schedule_default(Q)
+    finally:
+        lar.schedule_set(P, None)
+    assert lar.schedule_get(P) == d
+    # Tf/2 = 3072 over 256 threads is 12 values per thread; 4 x 1024 is not a
+    # wire shape; radix order 4 does not exist; 16 x 512 is 16 values of Wf 512
+    for bad in (dict(row_threads=256), dict(wire_cols=4, wire_threads=1024), dict(row_order=4),
+                dict(wire_order=-1), dict(wire_cols=16, wire_threads=512), dict(row_threads=300)):
+        with pytest.raises(lar.LarError) as e:
+            lar.schedule_set(P, dict(d, **bad))
+        assert e.value.status == lar.LAR_EINVAL
+    assert lar.schedule_get(P) == d
+    Q = inputs.cfg1_plane()
+    Q.nw_fft = 500                          # no 2^a 3^b plan
+    with pytest.raises(lar.LarError) as e:
+        lar.schedule_default(Q)
+    assert e.value.status == lar.LAR_ESIZE
+
+
+def test_schedule_candidates_every_shape_valid(lar):
+    # every listed candidate is accepted by lar_schedule_set, for small and
+    # large transforms; the power-of-8 wire length lists one radix order
+    for P in (inputs.cfg0_plane(), inputs.cfg1_plane(), inputs.Plane(n_wires=800, n_ticks=6000),
+              inputs.Plane(n_wires=3, n_ticks=2, n_imp=1, nt_fft=2, nw_fft=3),
+              inputs.Plane(n_wires=10, n_ticks=16000, n_imp=2, nt_fft=16384, nw_fft=16)):
+        cands = lar.schedule_candidates(P)
+        assert cands
+        try:
+            for c in cands:
+                lar.schedule_set(P, c)
+                assert lar.schedule_get(P) == c
+        finally:
+            lar.schedule_set(P, None)
+    wire_orders = {c["wire_order"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
+    assert wire_orders == {0, 1}            # 512 = 8^3: orders 2 and 3 repeat order 0
