@@ -64,6 +64,8 @@ def _stage_times(plane, grid, resp, wave, ws, reps, stream):
     """Median (rows ms, wire ms) over reps runs of lar_fftconv."""
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     start = torch.cuda.Event(enable_timing=True)
+    for e in ev:                  # torch creates the HIP event on its first record
+        e.record(stream)
     rows, wire = [], []
     lar.set_stage_events(ev)
     try:

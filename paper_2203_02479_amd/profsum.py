@@ -1,0 +1,126 @@
+"""Summaries of rocprofv3 output for the kernels of this package.
+
+    python -m paper_2203_02479_amd.profsum stats DIR
+        per-kernel calls / average / total time from a --kernel-trace --stats run
+    python -m paper_2203_02479_amd.profsum pmc DIR COUNTER [--last N]
+        per-kernel mean of COUNTER over the last N dispatches of each kernel
+        (a --pmc run; FETCH_SIZE / WRITE_SIZE are KiB per dispatch)
+    python -m paper_2203_02479_amd.profsum traffic FETCH_DIR WRITE_DIR CALIB_FETCH_DIR CALIB_WRITE_DIR
+        HBM bytes per launch of each bench stage, each counter scaled by what
+        it reads for a plain device copy of known size (bench.py --calib),
+        printed as JSON for bench.py --traffic
+
+DIR is searched recursively for the CSV files rocprofv3 writes.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import re
+import statistics
+import sys
+
+# bench stage -> kernel name pattern of the timed single-plane step
+STAGE_KERNELS = {
+    "fill": r"k_fill_zero\b",
+    "raster": r"k_raster<1>|k_raster<2>|k_raster<0>",
+    "r2c": r"k_r2c_rows",
+    "wire": r"k_wire_fused",
+    "c2r": r"k_c2r_rows",
+}
+CALIB_BYTES = 4 * (1 << 28)          # bench.py --calib copies 1 GiB of float32
+
+
+def _find(d, suffix):
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def _short(name):
+    name = re.sub(r"\(.*$", "", name)          # drop the argument list
+    name = name.replace("void ", "").replace("lar::", "")
+    return name
+
+
+def stats(d):
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    out = []
+    for r in rows:
+        out.append((_short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                    float(r["TotalDurationNs"]) / 1e6))
+    return out
+
+
+def pmc(d, counter, last=2):
+    """{kernel: mean counter value over its last `last` dispatches}."""
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    per = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        k = _short(r["Kernel_Name"])
+        per.setdefault(k, []).append((int(r.get("Dispatch_Id", 0)), float(r["Counter_Value"])))
+    out = {}
+    for k, v in per.items():
+        v.sort()
+        out[k] = statistics.mean(x for _, x in v[-last:])
+    return out
+
+
+def _copy_value(m):
+    """The counter of the largest copy-like kernel of the calibration run."""
+    cands = {k: v for k, v in m.items() if re.search(r"copy|Copy|elementwise", k)}
+    if not cands:
+        cands = m
+    return max(cands.values())
+
+
+def traffic(fd, wd, cfd, cwd):
+    f, w = pmc(fd, "FETCH_SIZE"), pmc(wd, "WRITE_SIZE")
+    cf, cw = _copy_value(pmc(cfd, "FETCH_SIZE", last=3)), _copy_value(pmc(cwd, "WRITE_SIZE", last=3))
+    # KiB per dispatch -> bytes, then scaled so the copy reads/writes its own size
+    kf = CALIB_BYTES / (cf * 1024.0)
+    kw = CALIB_BYTES / (cw * 1024.0)
+    out = {"_calibration": {"copy_bytes": CALIB_BYTES, "fetch_kib": cf, "write_kib": cw,
+                            "fetch_scale": kf, "write_scale": kw}}
+    for stage, pat in STAGE_KERNELS.items():
+        ks = [k for k in f if re.search(pat, k)]
+        if not ks:
+            continue
+        k = max(ks, key=lambda x: f[x])          # the dominant instantiation
+        rd = f[k] * 1024.0 * kf
+        wr = w.get(k, 0.0) * 1024.0 * kw
+        out[stage] = {"kernel": k, "read_bytes": round(rd), "write_bytes": round(wr),
+                      "bytes": round(rd + wr)}
+    return out
+
+
+def main(argv):
+    if len(argv) < 2:
+        print(__doc__)
+        return 2
+    cmd = argv[0]
+    if cmd == "stats":
+        print(f"{'calls':>6} {'avg_us':>10} {'total_ms':>10}  kernel")
+        for name, calls, avg, tot in sorted(stats(argv[1]), key=lambda r: -r[3]):
+            print(f"{calls:6d} {avg:10.2f} {tot:10.3f}  {name}")
+    elif cmd == "pmc":
+        last = 2
+        if "--last" in argv:
+            last = int(argv[argv.index("--last") + 1])
+        for k, v in sorted(pmc(argv[1], argv[2], last).items(), key=lambda kv: -kv[1]):
+            print(f"{v:16.1f}  {k}")
+    elif cmd == "traffic":
+        print(json.dumps(traffic(*argv[1:5]), indent=1))
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

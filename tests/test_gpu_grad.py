@@ -12,8 +12,9 @@ RTOL_GRAD = 1e-4
 
 
 def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(b)    # complex arrays keep their imaginary part
+    a = np.asarray(a, np.complex128 if cplx else np.float64)
+    b = np.asarray(b, np.complex128 if cplx else np.float64)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
