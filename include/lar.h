@@ -103,8 +103,10 @@ int lar_last_hip_error(void);
  * the grid, depend on scheduling (fluctuated counts are integers and sum
  * exactly below 2^24).
  * Workspace: none for the mean patch (ws may be NULL); a fluctuated raster
- * queues the bins that need the full rejection samplers in it.
- * lar_raster_workspace gives the recommended size for n_depos; any size of
+ * queues in it (16 bytes each) the rejection-regime bins that the first
+ * try's immediate acceptance does not decide, and draws them in a second
+ * kernel.  lar_raster_workspace gives the recommended size for n_depos
+ * (room for 48 such bins per depo); any size of
  * at least the size it gives for n_depos = depos->n with a queue of zero
  * (the sum of a 256-byte header and one byte per 16 depos, rounded up to
  * 256) is accepted and gives the same counts, a smaller queue only moves

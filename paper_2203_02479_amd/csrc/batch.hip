@@ -106,7 +106,7 @@ int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, in
     }
     L.raster = off;
     if (fluct && fluct->mode != 0)
-        off += raster_ws_fixed_subs(L.total_sub) + al(((size_t)total_depos * 16 + 4096) * kDeferredBytes);
+        off += raster_ws_fixed_subs(L.total_sub) + al(((size_t)total_depos * 48 + 4096) * kDeferredBytes);
     L.total = off;
     return LAR_OK;
 }

@@ -108,12 +108,13 @@ static size_t raster_bytes_min(int64_t n, const lar_fluct* f) {
     return raster_ws_fixed(n);
 }
 
-// recommended: room for 16 deferred bins per depo (a few per depo are
-// typical) plus a margin
+// recommended: room for 48 deferred bins per depo (rejection-regime bins
+// that the first sampler stage leaves; about 22 per depo on track depos of
+// 2300 electrons) plus a margin
 static size_t raster_bytes(int64_t n, const lar_fluct* f) {
     size_t fixed = raster_bytes_min(n, f);
     if (!fixed) return 0;
-    return fixed + ((size_t)n * 16 + 4096) * kDeferredBytes;
+    return fixed + ((size_t)n * 48 + 4096) * kDeferredBytes;
 }
 
 int lar_raster_workspace(const lar_plane* plane, int64_t n_depos, const lar_fluct* fluct,

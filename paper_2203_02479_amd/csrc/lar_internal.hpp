@@ -258,7 +258,7 @@ struct RasterItem {
 int64_t raster_subchunks(int64_t n);
 size_t raster_ws_fixed_subs(int64_t nsub);
 size_t raster_ws_fixed(int64_t n);
-constexpr size_t kDeferredBytes = 24;
+constexpr size_t kDeferredBytes = 16;
 // main_done (optional): recorded on s right after the main raster kernel.
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,

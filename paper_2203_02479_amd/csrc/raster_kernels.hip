@@ -18,6 +18,8 @@
 // Poisson: inversion for lambda < 10, PTRS otherwise (Hormann 1993).  The
 // sampler is FP64 without contraction so that a CPU implementation of the
 // same steps makes the same decisions.
+#include <algorithm>
+
 #include "lar_internal.hpp"
 
 namespace lar {
@@ -105,6 +107,10 @@ __device__ __forceinline__ void stream_prime(PhiloxStream& s) {
 
 #define LAR_MAX_TRIES 1000
 
+// Mean (n min(p, 1-p), lambda) below which a count is drawn by inversion,
+// else by the rejection samplers.
+static constexpr double kInvMean = 10.0;
+
 // log k! - [(k + 1/2) log(k+1) - (k+1) + log(2 pi)/2]
 __device__ double stirling_tail(double k) {
 #pragma clang fp contract(off)
@@ -116,11 +122,24 @@ __device__ double stirling_tail(double k) {
 }
 
 // x^n for a non-negative integer n (held in a double): square-and-multiply
-// over the bits of n from the least significant, IEEE multiplies only.
+// over the bits of n from the least significant, IEEE multiplies only.  When
+// every active lane has the same n (the lanes of one depo) the bit loop runs
+// on scalar registers; the multiplies, and so the result, are the same.
 __device__ __forceinline__ double ipow_n(double x, double n) {
 #pragma clang fp contract(off)
     uint64_t e = (uint64_t)n;
     double r = 1.0, b = x;
+    const uint32_t lo0 = __builtin_amdgcn_readfirstlane((uint32_t)e);
+    const uint32_t hi0 = __builtin_amdgcn_readfirstlane((uint32_t)(e >> 32));
+    const uint64_t e0 = ((uint64_t)hi0 << 32) | lo0;
+    if (__ballot(e != e0) == 0) {
+        for (uint64_t es = e0; es; ) {
+            if (es & 1u) r = r * b;
+            es >>= 1;
+            if (es) b = b * b;
+        }
+        return r;
+    }
     while (e) {
         if (e & 1u) r = r * b;
         e >>= 1;
@@ -293,9 +312,14 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s) {
 // decided by the fast region, the bounds test or the explicit pmf ratio
 // (|k - m| <= 15); returns -1 as soon as a try needs the log-scale test, or
 // after kFastTries tries.  The full sampler then redraws the bin from its
-// counter and reaches the same result.
+// counter and reaches the same result.  TRIES limits the tries: with
+// kTryAccept only the first try's immediate-acceptance region is taken (-1
+// otherwise), with 1 the whole first try: cheap stages that most bins finish
+// in, run apart so that a wave's lanes stay converged.
 static constexpr int kFastTries = 4;
+static constexpr int kTryAccept = 0;
 
+template <int TRIES>
 __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double npq = n * p * (1.0 - p);
@@ -307,13 +331,14 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
     double urvr = 0.86 * vr;
     double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
     bool slow_ready = false;
-    for (int tries = 0; tries < kFastTries; ++tries) {
+    for (int tries = 0; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
         double v = next_uniform(s);
         double u;
         if (v <= urvr) {
             u = v / vr - 0.43;
             return floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
         }
+        if (TRIES == kTryAccept) return -1.0;
         if (!slow_ready) {
             m = floor((n + 1.0) * p);
             r = p / (1.0 - p);
@@ -342,28 +367,61 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
 // PTRS without its logarithmic acceptance test (same tries and decisions as
 // poisson_ptrs while each try is decided by the immediate acceptance or the
 // cheap rejection); -1 when a try needs the log test or after kFastTries.
+// TRIES as for binom_btrd_fast.
+template <int TRIES>
 __device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double slam = sqrt(lam);
     double b = 0.931 + 2.53 * slam;
     double a = -0.059 + 0.02483 * b;
     double vr = 0.9277 - 3.6224 / (b - 2.0);
-    for (int tries = 0; tries < kFastTries; ++tries) {
+    for (int tries = 0; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
         double u = next_uniform(s) - 0.5;
         double v = next_uniform(s);
         double us = 0.5 - fabs(u);
         double k = floor((2.0 * a / us + b) * u + lam + 0.43);
         if (us >= 0.07 && v <= vr) return k;
+        if (TRIES == kTryAccept) return -1.0;
         if (k < 0.0 || (us < 0.013 && v > us)) continue;
         return -1.0;
     }
     return -1.0;
 }
 
+// The opening test of the inversion samplers for a small mean (n p < 1,
+// lam < 1): 0 when the first uniform lies below the lower bound of the
+// probability of 0 (the same test, on the same uniform, as in
+// binom_inversion / poisson_inversion), -1 when the full search is needed.
+__device__ __forceinline__ double binom_zero_test(double n, double p, PhiloxStream& s) {
+#pragma clang fp contract(off)
+    double u = next_uniform(s);
+    double np = n * p;
+    if (np < 1.0 && u < (1.0 - np) - (n + 64.0) * 8.8817841970012523e-16) return 0.0;
+    return -1.0;
+}
+
+__device__ __forceinline__ double poisson_zero_test(double lam, PhiloxStream& s) {
+#pragma clang fp contract(off)
+    double u = next_uniform(s);
+    if (lam < 1.0 && u < (1.0 - lam) - 1e-13) return 0.0;
+    return -1.0;
+}
+
 // Signed count of one bin drawn with inversion or the rejection samplers'
 // fast region only; returns NaN when the bin needs the full rejection
 // sampler (bin_count_in<true>, which redraws it from the same counter).
-template <int MODE>
+// Stages (a bin of a given regime may be drawn by the cheap stage first and,
+// when that returns NaN, by the full one from the same counter, with the
+// same result as the full stage alone):
+//   kStageZero  small-mean bins: the zero test only
+//   kStageInv   every non-rejection bin: the full inversion
+//   kStageFirst  rejection bins: the first try's immediate acceptance only
+//   kStageSecond rejection bins: the whole first try
+//   kStageRej    rejection bins: the fast rejection sampler
+//   kStageAll    any bin: inversion or the fast rejection sampler by regime
+enum { kStageZero = 0, kStageInv = 1, kStageFirst = 2, kStageRej = 3, kStageAll = 4, kStageSecond = 5 };
+
+template <int MODE, int STAGE>
 __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
                                                 uint32_t event, uint32_t bin, uint32_t plane,
                                                 const double* rtab = nullptr) {
@@ -382,7 +440,19 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
         } else {
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
-            double k = (n * pp < 10.0) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast(n, pp, s);
+            double k;
+            if (STAGE == kStageZero)
+                k = binom_zero_test(n, pp, s);
+            else if (STAGE == kStageFirst)
+                k = binom_btrd_fast<kTryAccept>(n, pp, s);
+            else if (STAGE == kStageSecond)
+                k = binom_btrd_fast<1>(n, pp, s);
+            else if (STAGE == kStageRej)
+                k = binom_btrd_fast<kFastTries>(n, pp, s);
+            else if (STAGE == kStageInv)
+                k = binom_inversion(n, pp, s, rtab);
+            else
+                k = (n * pp < kInvMean) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast<kFastTries>(n, pp, s);
             if (k < 0.0) return __builtin_nanf("");
             r = flip ? n - k : k;
         }
@@ -391,7 +461,18 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
         if (!(lam > 0.0)) {
             r = 0.0;
         } else {
-            r = (lam < 10.0) ? poisson_inversion(lam, s) : poisson_ptrs_fast(lam, s);
+            if (STAGE == kStageZero)
+                r = poisson_zero_test(lam, s);
+            else if (STAGE == kStageFirst)
+                r = poisson_ptrs_fast<kTryAccept>(lam, s);
+            else if (STAGE == kStageSecond)
+                r = poisson_ptrs_fast<1>(lam, s);
+            else if (STAGE == kStageRej)
+                r = poisson_ptrs_fast<kFastTries>(lam, s);
+            else if (STAGE == kStageInv)
+                r = poisson_inversion(lam, s);
+            else
+                r = (lam < kInvMean) ? poisson_inversion(lam, s) : poisson_ptrs_fast<kFastTries>(lam, s);
             if (r < 0.0) return __builtin_nanf("");
         }
     }
@@ -409,10 +490,35 @@ __device__ __forceinline__ bool rejection_regime(int mode, float q, double p) {
         double n = rint(aq);
         if (!(n > 0.0) || !(p > 0.0) || p >= 1.0) return false;
         double pp = p > 0.5 ? 1.0 - p : p;
-        return !(n * pp < 10.0);
+        return !(n * pp < kInvMean);
     }
     double lam = aq * p;
-    return lam > 0.0 && !(lam < 10.0);
+    return lam > 0.0 && !(lam < kInvMean);
+}
+
+// Wave-local stacks of k_raster, by the first sampler stage of a bin:
+//   kStkZ  small mean (mode 1: n min(p,1-p) < 1; mode 2: lam < 1) and bins
+//          without randomness (n = 0, p = 0, p >= 1): kStageZero
+//   kStkI  mean in [1, 4): kStageInv       kStkJ  mean in [4, 10): kStageInv
+//   kStkF  the rejection regime (mean >= 10): kStageFirst
+// Inversion takes about mean + 1 steps; splitting its bins at a mean of 4
+// keeps the steps of the lanes of one batch close together.
+enum { kStkZ = 0, kStkI = 1, kStkJ = 2, kStkF = 3, kStacks = 4 };
+
+__device__ __forceinline__ int sampler_stack(int mode, float q, double p) {
+#pragma clang fp contract(off)
+    double aq = fabs((double)q);
+    double mean;
+    if (mode == 1) {
+        double n = rint(aq);
+        if (!(n > 0.0) || !(p > 0.0) || p >= 1.0) return kStkZ;
+        double pp = p > 0.5 ? 1.0 - p : p;
+        mean = n * pp;
+    } else {
+        mean = aq * p;
+        if (!(mean > 0.0)) return kStkZ;
+    }
+    return !(mean < kInvMean) ? kStkF : mean < 1.0 ? kStkZ : mean < 4.0 ? kStkI : kStkJ;
 }
 
 // Signed count of one bin, for a bin known to be in the given regime.
@@ -580,13 +686,13 @@ static constexpr int kWaveTile = 1024;    // floats of a wave's private tile
 static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
 static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
-// Deferred bin: item, depo index within the item, impact row, tick, bin
-// probability (float).
+// Deferred bin: item, depo index within the item, bin index m * n_ticks + j
+// (the bin's counter word), bin probability (float).
 struct DeferredBin {
-    uint32_t item, depo, m, j;
+    uint32_t item, depo, bin;
     float p;
-    uint32_t pad;
 };
+static_assert(sizeof(DeferredBin) == kDeferredBytes, "queue record size");
 
 // Workspace of a fluctuated raster: header, one flag byte per sub-chunk,
 // then the queue.  The queue capacity is whatever the workspace holds.
@@ -645,7 +751,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
     __shared__ float s_q[kWaves][kSub];
     __shared__ int s_off[kWaves][FLUCT ? kSub + 1 : 1];
     __shared__ uint16_t s_queue[kWaves][FLUCT ? kWaveQueue : 1];   // (depo:4 | row:5 | tick:4)
-    __shared__ uint16_t s_list[kWaves][2][FLUCT ? 128 : 1];          // cells by sampler regime
+    __shared__ uint16_t s_list[kWaves][kStacks][FLUCT ? 128 : 1];    // cells by sampler stack
     __shared__ double s_rcp[FLUCT ? 112 : 1];                        // 1/k, k < 112
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -700,8 +806,11 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             }
             jlo_[lane] = jlo; nt_[lane] = nt; mlo_[lane] = mlo; nx_[lane] = nx; q_[lane] = q;
         }
-        const int jmin = wave_min(bj0), jmax = wave_max(bj1);
-        const int mmin = wave_min(bm0), mmax = wave_max(bm1);
+        // wave-uniform bounds, held in scalar registers
+        const int jmin = __builtin_amdgcn_readfirstlane(wave_min(bj0));
+        const int jmax = __builtin_amdgcn_readfirstlane(wave_max(bj1));
+        const int mmin = __builtin_amdgcn_readfirstlane(wave_min(bm0));
+        const int mmax = __builtin_amdgcn_readfirstlane(wave_max(bm1));
         if (jmax < jmin) continue;   // no regular depo in this sub-chunk (uniform)
         const int span_t = jmax - jmin + 1, span_x = mmax - mmin + 1;
         const bool use_tile = span_t * span_x <= kWaveTile;
@@ -760,118 +869,153 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             }
         } else {
             // ---- fluctuated patches.  Cells are classified 64 at a time by
-            // sampler regime into two wave-local stacks (inversion and
-            // rejection), and each stack is drawn in batches of 64 so that a
-            // wave runs one sampler at a time.  Rejection-regime bins that
-            // reach the log-scale test are queued for k_raster_deferred.
-            const int total = s_off[wv][kSub];
-            uint16_t* LI = s_list[wv][0];
-            uint16_t* LR = s_list[wv][1];
-            int nI = 0, nR = 0, nq = 0;   // wave-uniform stack and queue sizes
+            // sampler stage into four wave-local stacks, and each stack is
+            // drawn in batches of 64 so that a wave runs one sampler stage at
+            // a time:
+            //   Z  small-mean bins (n p < 1, lam < 1) and degenerate ones:
+            //      the zero test only; a bin that fails it moves to I
+            //   I, J  inversion bins of mean below / above 4: the full inversion
+            //   F  rejection bins: the first try's immediate acceptance; a bin
+            //      that needs more is queued for k_raster_deferred, which runs
+            //      the rest of the rejection sampler (its registers would
+            //      otherwise bound this kernel's occupancy).
+            // A moved or queued bin is redrawn from its counter, so every
+            // stage reaches the count of the one-shot sampler.  Stacks hold
+            // up to 128 codes.  A batch is drawn from the first stack, in the
+            // order I, J, Z, F, that holds 64 codes or more (any, once every
+            // cell is classified); new cells are classified only when all
+            // stacks hold fewer than 64.  I comes before Z, which pushes into
+            // it, so every push of up to 64 codes fits.
+            const int total = __builtin_amdgcn_readfirstlane(s_off[wv][kSub]);
+            uint16_t* const L0 = s_list[wv][0];   // stack k at L0 + 128 k
+            int nL[kStacks] = {0, 0, 0, 0};   // wave-uniform stack sizes
+            int nq = 0;                 // wave-uniform queue size
             int d = 0;
             int c0 = 0;
-            while (c0 < total || nI > 0 || nR > 0) {
-                if (c0 < total) {
-                    const int c = c0 + lane;
-                    bool isI = false, isR = false;
-                    int code = 0;
-                    if (c < total) {
-                        while (s_off[wv][d + 1] <= c) ++d;
-                        const int ant = abs(nt_[d]);
-                        const int local = c - s_off[wv][d];
-                        const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
-                        const int b = local - a * ant;
-                        const float* w = W + d * kSlot;
-                        const double p = (double)(w[b] * w[kMaxT + a]);
-                        code = (d << 9) | (a << 4) | b;
-                        isR = rejection_regime(MODE, q_[d], p);
-                        isI = !isR;
+            // one batch of 64 (or the rest) from stack st
+            auto batch = [&](const int st) {   // st is wave-uniform
+                wave_lds_sync();
+                const int cnt = min(nL[st], 64);
+                int todo = -1, code = 0;
+                bool defer = false, move = false;
+                float v = 0.f;
+                if (lane < cnt) {
+                    code = L0[st * 128 + nL[st] - cnt + lane];
+                    const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
+                    const float* w = W + dd * kSlot;
+                    const int j = jlo_[dd] + b;
+                    const int m = mlo_[dd] + a;
+                    const double p = (double)(w[b] * w[kMaxT + a]);
+                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                    const uint32_t dg = (uint32_t)(base + dd);
+                    if (st == kStkZ)
+                        v = bin_count_fast<MODE, kStageZero>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                    else if (st == kStkF)
+                        v = bin_count_fast<MODE, kStageFirst>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                    else
+                        v = bin_count_fast<MODE, kStageInv>(q_[dd], p, A.seed, dg, A.event, bin, A.plane,
+                                                            s_rcp);
+                    if (v != v) {
+                        if (st == kStkF) defer = true;
+                        else move = true;
+                    } else if (v != 0.f) {
+                        todo = dd;
                     }
-                    const uint64_t mI = __ballot(isI), mR = __ballot(isR);
-                    const uint64_t below = (1ull << lane) - 1;
-                    if (isI) LI[nI + __popcll(mI & below)] = (uint16_t)code;
-                    if (isR) LR[nR + __popcll(mR & below)] = (uint16_t)code;
-                    nI += __popcll(mI);
-                    nR += __popcll(mR);
-                    c0 += 64;
                 }
+                nL[st] -= cnt;
+                const uint64_t below = (1ull << lane) - 1;
+                if (st == kStkZ) {   // failed zero tests go to the low-mean inversion stack
+                    const uint64_t mm = __ballot(move);
+                    if (move) L0[kStkI * 128 + nL[kStkI] + __popcll(mm & below)] = (uint16_t)code;
+                    nL[kStkI] += __popcll(mm);
+                }
+                if (st == kStkF) {
+                    const uint64_t dm = __ballot(defer);
+                    if (defer) s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)code;
+                    nq += __popcll(dm);
+                }
+                // add the drawn counts, the lanes of one depo at a time (cells of
+                // one depo are distinct; two depos may share a cell)
+                uint64_t rem = __ballot(todo >= 0);
+                while (rem) {
+                    const int dd = __builtin_amdgcn_readlane(todo, __ffsll((long long)rem) - 1);
+                    const bool mine = todo == dd;
+                    rem &= ~__ballot(mine);
+                    if (mine) {   // the cell, recomputed from the code
+                        const int m = mlo_[dd] + ((code >> 4) & 31), j = jlo_[dd] + (code & 15);
+                        if (use_tile)
+                            tile[(m - mmin) * span_t + (j - jmin)] += v;
+                        else
+                            atomicAdd(&grid[(int64_t)m * A.ld + j], v);
+                    }
+                    asm volatile("" ::: "memory");
+                }
+                // move queued bins to the workspace when the next batch could
+                // overflow the buffer, and at the end of the sub-chunk
+                const bool last = c0 >= total && nL[0] == 0 && nL[1] == 0 && nL[2] == 0 && nL[3] == 0;
+                if (nq > kWaveQueue - 64 || (last && nq > 0)) {
+                    wave_lds_sync();
+                    unsigned long long gb = 0;
+                    if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
+                    gb = __shfl(gb, 0, 64);
+                    const bool fits = gb + (unsigned long long)nq <= cap;
+                    for (int e = lane; e < nq; e += 64) {
+                        const unsigned long long slot = gb + (unsigned long long)e;
+                        if (slot >= cap) continue;
+                        DeferredBin db;
+                        db.item = (uint32_t)it;
+                        if (fits) {
+                            const int cd = s_queue[wv][e];
+                            const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                            const float* w = W + dq * kSlot;
+                            db.depo = (uint32_t)(base + dq);
+                            db.bin = (uint32_t)((int64_t)(mlo_[dq] + a) * A.n_ticks + (jlo_[dq] + b));
+                            db.p = w[b] * w[kMaxT + a];
+                        } else {
+                            db.depo = kInvalid; db.bin = 0; db.p = 0.f;
+                        }
+                        queue[slot] = db;
+                    }
+                    if (!fits && lane == 0) flags[gsub] = 1;
+                    nq = 0;
+                    wave_lds_sync();
+                }
+            };
+            for (;;) {
                 const bool tail = c0 >= total;
-                for (int which = 0; which < 2; ++which) {
-                    uint16_t* L = which ? LR : LI;
-                    int& nL = which ? nR : nI;
-                    while (nL >= 64 || (tail && nL > 0)) {
-                        wave_lds_sync();
-                        const int cnt = min(nL, 64);
-                        int m = 0, j = 0, todo = -1, code = 0;
-                        bool defer = false;
-                        float v = 0.f;
-                        if (lane < cnt) {
-                            code = L[nL - cnt + lane];
-                            const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
-                            const float* w = W + dd * kSlot;
-                            j = jlo_[dd] + b;
-                            m = mlo_[dd] + a;
-                            const double p = (double)(w[b] * w[kMaxT + a]);
-                            const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                            v = bin_count_fast<MODE>(q_[dd], p, A.seed, (uint32_t)(base + dd), A.event,
-                                                     bin, A.plane, s_rcp);
-                            if (v != v) {
-                                defer = true;
-                            } else if (v != 0.f) {
-                                todo = dd;
-                            }
-                        }
-                        nL -= cnt;
-                        const uint64_t dm = __ballot(defer);
-                        if (defer) s_queue[wv][nq + __popcll(dm & ((1ull << lane) - 1))] = (uint16_t)code;
-                        nq += __popcll(dm);
-                        // add the drawn counts, the lanes of one depo at a time
-                        for (;;) {
-                            const int first = wave_min(todo < 0 ? INT_MAX : todo);
-                            if (first == INT_MAX) break;
-                            if (todo == first) {
-                                if (use_tile)
-                                    tile[(m - mmin) * span_t + (j - jmin)] += v;
-                                else
-                                    atomicAdd(&grid[(int64_t)m * A.ld + j], v);
-                                todo = -1;
-                            }
-                            asm volatile("" ::: "memory");
-                        }
-                        // move queued bins to the workspace when the next batch
-                        // could overflow the buffer, and at the end
-                        const bool last = tail && nI == 0 && nR == 0;
-                        if (nq > kWaveQueue - 64 || (last && nq > 0)) {
-                            wave_lds_sync();
-                            unsigned long long gb = 0;
-                            if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
-                            gb = __shfl(gb, 0, 64);
-                            const bool fits = gb + (unsigned long long)nq <= cap;
-                            for (int e = lane; e < nq; e += 64) {
-                                const unsigned long long slot = gb + (unsigned long long)e;
-                                if (slot >= cap) continue;
-                                DeferredBin db;
-                                db.item = (uint32_t)it;
-                                db.pad = 0u;
-                                if (fits) {
-                                    const int cd = s_queue[wv][e];
-                                    const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
-                                    const float* w = W + dq * kSlot;
-                                    db.depo = (uint32_t)(base + dq);
-                                    db.m = (uint32_t)(mlo_[dq] + a);
-                                    db.j = (uint32_t)(jlo_[dq] + b);
-                                    db.p = w[b] * w[kMaxT + a];
-                                } else {
-                                    db.depo = kInvalid; db.m = 0; db.j = 0; db.p = 0.f;
-                                }
-                                queue[slot] = db;
-                            }
-                            if (!fits && lane == 0) flags[gsub] = 1;
-                            nq = 0;
-                            wave_lds_sync();
-                        }
-                    }
+                const int thr = tail ? 1 : 64;
+                const int st = nL[kStkI] >= thr   ? kStkI
+                               : nL[kStkJ] >= thr ? kStkJ
+                               : nL[kStkZ] >= thr ? kStkZ
+                               : nL[kStkF] >= thr ? kStkF
+                                                  : -1;
+                if (st >= 0) {
+                    batch(st);
+                    continue;
                 }
+                if (tail) break;
+                // classify the next 64 cells (every stack holds < 64)
+                const int c = c0 + lane;
+                int sk = -1, code = 0;
+                if (c < total) {
+                    while (s_off[wv][d + 1] <= c) ++d;
+                    const int ant = abs(nt_[d]);
+                    const int local = c - s_off[wv][d];
+                    const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
+                    const int b = local - a * ant;
+                    const float* w = W + d * kSlot;
+                    const double p = (double)(w[b] * w[kMaxT + a]);
+                    code = (d << 9) | (a << 4) | b;
+                    sk = sampler_stack(MODE, q_[d], p);
+                }
+                const uint64_t below = (1ull << lane) - 1;
+#pragma unroll
+                for (int k = 0; k < kStacks; ++k) {
+                    const uint64_t mk = __ballot(sk == k);
+                    if (sk == k) L0[k * 128 + nL[k] + __popcll(mk & below)] = (uint16_t)code;
+                    nL[k] += __popcll(mk);
+                }
+                c0 += 64;
             }
         }
         // ---- flush: one global atomic per non-zero cell, leave the tile zeroed
@@ -896,31 +1040,103 @@ __global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
     for (; i < nsub; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
-// The queued bins with the full rejection samplers (skipping bins of
-// sub-chunks left to k_raster_overflow).
+// The queued bins (skipping those of sub-chunks left to k_raster_overflow),
+// in three converged stages per wave: every bin first runs the whole first
+// try of the rejection sampler; the bins it leaves run the fast sampler
+// (from the start: the same tries, up to kFastTries); the bins that leaves
+// (log-scale test) run the full sampler.  Each later stage collects its bins
+// in a wave-local stack and draws them 64 at a time.  A bin's count depends
+// only on its counter, so the stage that draws it does not change it.
+static constexpr int kDefWaves = 4;
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_raster_deferred(RasterItem one, const RasterItem* __restrict__ items,
-                                                         const RasterWs* __restrict__ ws,
-                                                         const uint8_t* __restrict__ flags,
-                                                         const DeferredBin* __restrict__ queue,
-                                                         unsigned long long cap) {
+__device__ __forceinline__ void deferred_draw(const RasterItem& one, const RasterItem* items,
+                                              const DeferredBin& db, int stage, float& v) {
+    const RasterItem& I = items ? items[db.item] : one;
+    const RasterArgs& A = I.A;
+    const float q = I.q[db.depo];
+    const double p = (double)db.p;
+    if (stage == 0)
+        v = bin_count_fast<MODE, kStageSecond>(q, p, A.seed, db.depo, A.event, db.bin, A.plane);
+    else if (stage == 1)
+        v = bin_count_fast<MODE, kStageRej>(q, p, A.seed, db.depo, A.event, db.bin, A.plane);
+    else
+        v = bin_count_in<true>(MODE, q, p, A.seed, db.depo, A.event, db.bin, A.plane);
+}
+
+template <int MODE>
+__device__ __forceinline__ void deferred_add(const RasterItem& one, const RasterItem* items,
+                                             const DeferredBin& db, float v) {
+    const RasterItem& I = items ? items[db.item] : one;
+    const int64_t m = db.bin / (uint32_t)I.A.n_ticks, j = db.bin - m * I.A.n_ticks;
+    atomicAdd(&I.grid[m * I.A.ld + j], v);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
+    RasterItem one, const RasterItem* __restrict__ items, const RasterWs* __restrict__ ws,
+    const uint8_t* __restrict__ flags, const DeferredBin* __restrict__ queue, unsigned long long cap) {
+    __shared__ uint32_t s_stk[kDefWaves][2][128];   // queue indices of stages 1 and 2
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t* S1 = s_stk[wv][0];
+    uint32_t* S2 = s_stk[wv][1];
     const unsigned long long cnt = min(ws->count, cap);
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        const DeferredBin db = queue[i];
-        if (db.depo == kInvalid) continue;
-        const RasterItem& I = items ? items[db.item] : one;
-        if (flags[I.sub_begin + db.depo / kSub]) continue;
-        const RasterArgs& A = I.A;
-        const uint32_t bin = (uint32_t)((int64_t)db.m * A.n_ticks + db.j);
-        const float v = bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo, A.event,
-                                           bin, A.plane);
-        if (v != 0.f) atomicAdd(&I.grid[(int64_t)db.m * A.ld + db.j], v);
+    const unsigned long long nchunk = (cnt + 63) / 64;
+    int n1 = 0, n2 = 0;   // wave-uniform
+    const uint64_t below = (1ull << lane) - 1;
+    // one batch of 64 (or the rest) from the stage-1 or stage-2 stack
+    auto batch = [&](int stage) {
+        uint32_t* S = stage == 1 ? S1 : S2;
+        int& n = stage == 1 ? n1 : n2;
+        const int c = min(n, 64);
+        bool more = false;
+        uint32_t idx = 0;
+        if (lane < c) {
+            idx = S[n - c + lane];
+            const DeferredBin db = queue[idx];
+            float v;
+            deferred_draw<MODE>(one, items, db, stage, v);
+            if (v != v) more = true;   // stage 1 only: the log-scale test
+            else if (v != 0.f) deferred_add<MODE>(one, items, db, v);
+        }
+        n -= c;
+        if (stage == 1) {
+            const uint64_t mm = __ballot(more);
+            if (more) S2[n2 + __popcll(mm & below)] = idx;
+            n2 += __popcll(mm);
+        }
+    };
+    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;; ch += (unsigned long long)gridDim.x * kDefWaves) {
+        const bool tail = ch >= nchunk;
+        // drain: stage 2 before stage 1, which pushes into it
+        while (n2 >= 64 || (tail && n2 > 0)) batch(2);
+        while (n1 >= 64 || (tail && n1 > 0)) {
+            batch(1);
+            while (n2 >= 64 || (tail && n2 > 0)) batch(2);
+        }
+        if (tail) break;
+        const unsigned long long i = ch * 64 + lane;
+        bool more = false;
+        if (i < cnt) {
+            const DeferredBin db = queue[i];
+            const RasterItem& I = items ? items[db.item] : one;
+            if (db.depo != kInvalid && !flags[I.sub_begin + db.depo / kSub]) {
+                float v;
+                deferred_draw<MODE>(one, items, db, 0, v);
+                if (v != v) more = true;
+                else if (v != 0.f) deferred_add<MODE>(one, items, db, v);
+            }
+        }
+        const uint64_t mm = __ballot(more);
+        if (more) S1[n1 + __popcll(mm & below)] = (uint32_t)i;
+        n1 += __popcll(mm);
     }
 }
 
 // Sub-chunks whose deferred bins did not fit in the queue: recompute their
-// regular depos' bins and draw the deferred ones with the full samplers.
+// regular depos' bins and draw the deferred ones (rejection-regime bins
+// that the first try's immediate acceptance did not decide) with the full
+// samplers.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const RasterItem* __restrict__ items,
                                                          int n_items, int64_t total_sub,
@@ -947,8 +1163,9 @@ __global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const R
                 const int j = wt.lo + b, m = wx.lo + a;
                 const double p = (double)(wtv * wxv);
                 const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                float v = bin_count_fast<MODE>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                if (v != v) {
+                if (sampler_stack(MODE, q, p) != kStkF) continue;
+                float v = bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                if (v != v) {   // queued by k_raster: draw it here
                     v = bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                     if (v != 0.f) atomicAdd(&I.grid[(int64_t)m * A.ld + j], v);
                 }
@@ -1139,7 +1356,9 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     RasterWs* hdr = reinterpret_cast<RasterWs*>(ws);
     uint8_t* flags = reinterpret_cast<uint8_t*>(ws) + 256;
     DeferredBin* queue = reinterpret_cast<DeferredBin*>(reinterpret_cast<char*>(ws) + fixed);
-    const unsigned long long cap = (unsigned long long)((ws_bytes - fixed) / sizeof(DeferredBin));
+    // queue positions are 32-bit in k_raster_deferred's stacks
+    const unsigned long long cap =
+        std::min<unsigned long long>((ws_bytes - fixed) / sizeof(DeferredBin), 0xFFFFFFFFull);
     const int64_t rblk = (total_sub + 255) / 256;
     hipLaunchKernelGGL(k_raster_reset, dim3((unsigned)(rblk < cap_blocks ? rblk : cap_blocks)), dim3(256),
                        0, s, hdr, flags, total_sub);
@@ -1148,7 +1367,8 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
                        cap);                                                                         \
     if (main_done) (void)hipEventRecord(main_done, s);                                               \
-    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(256), 0, s, one, items, \
+    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s,  \
+                       one, items,                                                                   \
                        hdr, flags, queue, cap);                                                      \
     hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, one, items, n_items, total_sub,   \
                        flags);                                                                       \

@@ -55,8 +55,7 @@ def stats(d):
     return out
 
 
-def pmc(d, counter, last=2):
-    """{kernel: mean counter value over its last `last` dispatches}."""
+def _pmc_rows(d, counter):
     rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
     per = {}
     for r in rows:
@@ -64,11 +63,24 @@ def pmc(d, counter, last=2):
             continue
         k = _short(r["Kernel_Name"])
         per.setdefault(k, []).append((int(r.get("Dispatch_Id", 0)), float(r["Counter_Value"])))
-    out = {}
-    for k, v in per.items():
+    for v in per.values():
         v.sort()
-        out[k] = statistics.mean(x for _, x in v[-last:])
-    return out
+    return per
+
+
+def pmc(d, counter, last=2):
+    """{kernel: mean counter value over its last `last` dispatches}."""
+    return {k: statistics.mean(x for _, x in v[-last:]) for k, v in _pmc_rows(d, counter).items()}
+
+
+def last_dispatched(d, counter, pattern):
+    """The kernel matching pattern that was dispatched last (the instantiation
+    the timed steps at the end of the run used)."""
+    best, when = None, -1
+    for k, v in _pmc_rows(d, counter).items():
+        if re.search(pattern, k) and v[-1][0] > when:
+            best, when = k, v[-1][0]
+    return best
 
 
 def _copy_value(m):
@@ -88,10 +100,9 @@ def traffic(fd, wd, cfd, cwd):
     out = {"_calibration": {"copy_bytes": CALIB_BYTES, "fetch_kib": cf, "write_kib": cw,
                             "fetch_scale": kf, "write_scale": kw}}
     for stage, pat in STAGE_KERNELS.items():
-        ks = [k for k in f if re.search(pat, k)]
-        if not ks:
+        k = last_dispatched(fd, "FETCH_SIZE", pat)
+        if k is None:
             continue
-        k = max(ks, key=lambda x: f[x])          # the dominant instantiation
         rd = f[k] * 1024.0 * kf
         wr = w.get(k, 0.0) * 1024.0 * kw
         out[stage] = {"kernel": k, "read_bytes": round(rd), "write_bytes": round(wr),

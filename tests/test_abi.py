@@ -48,7 +48,7 @@ def test_workspace_queries_and_size_checks(lar):
     assert lar.sim_plane_workspace(P) == 4800 * 6000 * 4 + lar.fftconv_workspace(P)
     assert lar.raster_workspace(P, 1000, None) == 0
     fixed = 256 + ((1000 + 15) // 16 + 255) // 256 * 256
-    assert lar.raster_workspace(P, 1000, (1, 0, 0, 0)) == fixed + (1000 * 16 + 4096) * 24
+    assert lar.raster_workspace(P, 1000, (1, 0, 0, 0)) == fixed + (1000 * 48 + 4096) * 16
     assert (lar.sim_plane_workspace(P, 1000, (2, 0, 0, 0))
             == lar.sim_plane_workspace(P) + lar.raster_workspace(P, 1000, (2, 0, 0, 0)))
     for bad in (dict(nt_fft=6000 + 2 * 7), dict(nt_fft=5999), dict(nw_fft=500), dict(nw_fft=400),

@@ -272,7 +272,7 @@ def test_fluct_queue_capacity_does_not_change_counts(mode):
     full = gpu_raster(P, dep, fluct=fl)
     n = len(dep)
     fixed = 256 + ((n + 15) // 16 + 255) // 256 * 256
-    for nb in (fixed, fixed + 24 * 37):
+    for nb in (fixed, fixed + 16 * 37):
         assert np.array_equal(gpu_raster(P, dep, fluct=fl, ws_bytes=nb), full)
     with pytest.raises(lar.LarError):
         gpu_raster(P, dep, fluct=fl, ws_bytes=fixed - 256)
