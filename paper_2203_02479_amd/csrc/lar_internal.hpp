@@ -126,8 +126,18 @@ struct TwHalf {           // table h[k] = exp(-pi i k / n), k < n (half-angle ta
     }
 };
 
+// Padded LDS index of element i of a transform buffer: one unused slot
+// after every 16 complex elements.  The first Stockham passes write with a
+// stride of R (or R*NS) elements, a power of two that would put a
+// half-wave's 64-bit stores on a few of the 32 banks (12-way conflicts for
+// R = 8); the padding spreads them over all banks.
+constexpr int kPadShift = 4;
+__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> kPadShift); }
+// Elements a padded buffer of n elements occupies.
+__host__ __device__ __forceinline__ int lpad_n(int n) { return n + (n >> kPadShift) + 1; }
+
 // One Stockham pass over NS interleaved sequences held in LDS (element i of
-// sequence s at A[i*NS + s]).  All loads of a thread happen before the
+// sequence s at A[lpad(i*NS + s)]).  All loads of a thread happen before the
 // barrier and all stores after it, so the pass is in place.
 template <int R, int MAXB, int NS, class TW>
 __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid, int T,
@@ -146,7 +156,7 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
             int k = j % Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 x = A[(j + r * nb) * NS + s];
+                float2 x = A[lpad((j + r * nb) * NS + s)];
                 if (r > 0) {
                     float2 t = tw(r * k * stride);
                     x = inv ? cmulc(x, t) : cmul(x, t);
@@ -162,7 +172,7 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
         if (dst[b] >= 0) {
             dft_small<R>(v[b], inv);
 #pragma unroll
-            for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * NS] = v[b][r];
+            for (int r = 0; r < R; ++r) A[lpad(dst[b] + r * Ns * NS)] = v[b][r];
         }
     }
     lds_barrier();

@@ -110,6 +110,9 @@ __device__ __forceinline__ void stream_prime(PhiloxStream& s) {
 // Mean (n min(p, 1-p), lambda) below which a count is drawn by inversion,
 // else by the rejection samplers.
 static constexpr double kInvMean = 10.0;
+// Entries of the 1/k table of binom_inversion: k <= 111 is reached (the
+// search stops past 110) and the next entry is loaded one step ahead.
+static constexpr int kRcpTable = 113;
 
 // log k! - [(k + 1/2) log(k+1) - (k+1) + log(2 pi)/2]
 __device__ double stirling_tail(double k) {
@@ -167,14 +170,27 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
         if (tries > 0) u = next_uniform(s);
         double f = f0;
         double k = 0.0;
-        for (;;) {
-            if (u < f) return k;
-            if (k >= n || k > 110.0) break;
-            u = u - f;
-            k = k + 1.0;
-            // 1/k correctly rounded: from the table when given, else divided
-            const double ik = rtab ? rtab[(int)k] : 1.0 / k;
-            f = f * (g * ik - ratio);
+        if (rtab) {
+            // 1/k correctly rounded, from the table (kRcpTable entries); the
+            // next step's entry is loaded one step ahead
+            double ik_next = rtab[1];
+            for (int ki = 1;; ++ki) {
+                if (u < f) return k;
+                if (k >= n || k > 110.0) break;
+                u = u - f;
+                k = k + 1.0;
+                const double ik = ik_next;
+                ik_next = rtab[ki + 1];
+                f = f * (g * ik - ratio);
+            }
+        } else {
+            for (;;) {
+                if (u < f) return k;
+                if (k >= n || k > 110.0) break;
+                u = u - f;
+                k = k + 1.0;
+                f = f * (g * (1.0 / k) - ratio);
+            }
         }
     }
     return floor(n * p);
@@ -315,12 +331,17 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s) {
 // counter and reaches the same result.  TRIES limits the tries: with
 // kTryAccept only the first try's immediate-acceptance region is taken (-1
 // otherwise), with 1 the whole first try: cheap stages that most bins finish
-// in, run apart so that a wave's lanes stay converged.
+// in, run apart so that a wave's lanes stay converged.  Returns -1 when a try
+// needs the log-scale test, -2 when TRIES tries were rejected.
+//
+// A try that is not accepted at once takes exactly two uniforms, one Philox
+// block, so try t >= 1 starts at block t when every earlier try went past
+// its immediate acceptance: binom_btrd_fast_from resumes the sampler there.
 static constexpr int kFastTries = 4;
 static constexpr int kTryAccept = 0;
 
 template <int TRIES>
-__device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s) {
+__device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s, int from = 0) {
 #pragma clang fp contract(off)
     double npq = n * p * (1.0 - p);
     double spq = sqrt(npq);
@@ -331,7 +352,7 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
     double urvr = 0.86 * vr;
     double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
     bool slow_ready = false;
-    for (int tries = 0; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
+    for (int tries = from; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
         double v = next_uniform(s);
         double u;
         if (v <= urvr) {
@@ -361,21 +382,22 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
         if (km > 15.0) return -1.0;
         if (btrd_ratio_accept(v, k, m, nr, r)) return k;
     }
-    return -1.0;
+    return -2.0;
 }
 
 // PTRS without its logarithmic acceptance test (same tries and decisions as
 // poisson_ptrs while each try is decided by the immediate acceptance or the
 // cheap rejection); -1 when a try needs the log test or after kFastTries.
-// TRIES as for binom_btrd_fast.
+// TRIES, from and the return codes as for binom_btrd_fast (every PTRS try
+// takes one Philox block).
 template <int TRIES>
-__device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s) {
+__device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s, int from = 0) {
 #pragma clang fp contract(off)
     double slam = sqrt(lam);
     double b = 0.931 + 2.53 * slam;
     double a = -0.059 + 0.02483 * b;
     double vr = 0.9277 - 3.6224 / (b - 2.0);
-    for (int tries = 0; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
+    for (int tries = from; tries < (TRIES == kTryAccept ? 1 : TRIES); ++tries) {
         double u = next_uniform(s) - 0.5;
         double v = next_uniform(s);
         double us = 0.5 - fabs(u);
@@ -385,7 +407,7 @@ __device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s)
         if (k < 0.0 || (us < 0.013 && v > us)) continue;
         return -1.0;
     }
-    return -1.0;
+    return -2.0;
 }
 
 // The opening test of the inversion samplers for a small mean (n p < 1,
@@ -418,8 +440,14 @@ __device__ __forceinline__ double poisson_zero_test(double lam, PhiloxStream& s)
 //   kStageFirst  rejection bins: the first try's immediate acceptance only
 //   kStageSecond rejection bins: the whole first try
 //   kStageRej    rejection bins: the fast rejection sampler
+//   kStageResume rejection bins whose first try went past its immediate
+//                acceptance and was rejected: the fast rejection sampler
+//                from the second try (stream at block 1)
 //   kStageAll    any bin: inversion or the fast rejection sampler by regime
-enum { kStageZero = 0, kStageInv = 1, kStageFirst = 2, kStageRej = 3, kStageAll = 4, kStageSecond = 5 };
+// Undecided bins return NaN, or -infinity for kStageSecond when the first
+// try was rejected (the bin can resume; NaN there means the log-scale test).
+enum { kStageZero = 0, kStageInv = 1, kStageFirst = 2, kStageRej = 3, kStageAll = 4, kStageSecond = 5,
+       kStageResume = 6 };
 
 template <int MODE, int STAGE>
 __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
@@ -428,7 +456,11 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
-    stream_prime(s);
+    if (STAGE == kStageResume)
+        s.c3 += 1u;          // the second try's block
+    else
+        stream_prime(s);
+    const int from = STAGE == kStageResume ? 1 : 0;
     double aq = fabs((double)q);
     double r;
     if (MODE == 1) {
@@ -441,7 +473,9 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
             double k;
-            if (STAGE == kStageZero)
+            if (STAGE == kStageResume)
+                k = binom_btrd_fast<kFastTries>(n, pp, s, from);
+            else if (STAGE == kStageZero)
                 k = binom_zero_test(n, pp, s);
             else if (STAGE == kStageFirst)
                 k = binom_btrd_fast<kTryAccept>(n, pp, s);
@@ -453,6 +487,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
                 k = binom_inversion(n, pp, s, rtab);
             else
                 k = (n * pp < kInvMean) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast<kFastTries>(n, pp, s);
+            if (STAGE == kStageSecond && k == -2.0) return -__builtin_inff();
             if (k < 0.0) return __builtin_nanf("");
             r = flip ? n - k : k;
         }
@@ -461,7 +496,9 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
         if (!(lam > 0.0)) {
             r = 0.0;
         } else {
-            if (STAGE == kStageZero)
+            if (STAGE == kStageResume)
+                r = poisson_ptrs_fast<kFastTries>(lam, s, from);
+            else if (STAGE == kStageZero)
                 r = poisson_zero_test(lam, s);
             else if (STAGE == kStageFirst)
                 r = poisson_ptrs_fast<kTryAccept>(lam, s);
@@ -473,6 +510,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
                 r = poisson_inversion(lam, s);
             else
                 r = (lam < kInvMean) ? poisson_inversion(lam, s) : poisson_ptrs_fast<kFastTries>(lam, s);
+            if (STAGE == kStageSecond && r == -2.0) return -__builtin_inff();
             if (r < 0.0) return __builtin_nanf("");
         }
     }
@@ -699,6 +737,7 @@ static_assert(sizeof(DeferredBin) == kDeferredBytes, "queue record size");
 struct RasterWs {
     unsigned long long count;    // bins queued (may exceed the capacity)
 };
+static constexpr uint32_t kHardMark = 0x80000000u;   // DeferredBin::item bit: left to k_raster_hard
 
 int64_t raster_subchunks(int64_t n) { return (n + kSub - 1) / kSub; }
 
@@ -752,7 +791,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
     __shared__ int s_off[kWaves][FLUCT ? kSub + 1 : 1];
     __shared__ uint16_t s_queue[kWaves][FLUCT ? kWaveQueue : 1];   // (depo:4 | row:5 | tick:4)
     __shared__ uint16_t s_list[kWaves][kStacks][FLUCT ? 128 : 1];    // cells by sampler stack
-    __shared__ double s_rcp[FLUCT ? 112 : 1];                        // 1/k, k < 112
+    __shared__ double s_rcp[FLUCT ? kRcpTable : 1];                  // 1/k, k < kRcpTable
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float* W = s_w[wv];
@@ -764,7 +803,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
     float* q_ = s_q[wv];
     for (int i = lane; i < kWaveTile; i += 64) tile[i] = 0.f;
     if (FLUCT) {
-        for (int i = threadIdx.x; i < 112; i += kRasterThreads) s_rcp[i] = i ? 1.0 / (double)i : 0.0;
+        for (int i = threadIdx.x; i < kRcpTable; i += kRasterThreads) s_rcp[i] = i ? 1.0 / (double)i : 0.0;
         __syncthreads();
     }
 
@@ -934,21 +973,15 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     if (defer) s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)code;
                     nq += __popcll(dm);
                 }
-                // add the drawn counts, the lanes of one depo at a time (cells of
-                // one depo are distinct; two depos may share a cell)
-                uint64_t rem = __ballot(todo >= 0);
-                while (rem) {
-                    const int dd = __builtin_amdgcn_readlane(todo, __ffsll((long long)rem) - 1);
-                    const bool mine = todo == dd;
-                    rem &= ~__ballot(mine);
-                    if (mine) {   // the cell, recomputed from the code
-                        const int m = mlo_[dd] + ((code >> 4) & 31), j = jlo_[dd] + (code & 15);
-                        if (use_tile)
-                            tile[(m - mmin) * span_t + (j - jmin)] += v;
-                        else
-                            atomicAdd(&grid[(int64_t)m * A.ld + j], v);
-                    }
-                    asm volatile("" ::: "memory");
+                // add the drawn counts: two depos of one batch may share a cell,
+                // so the tile takes LDS atomics here (cheaper than serialising
+                // the lanes by depo, measured)
+                if (todo >= 0) {   // the cell, recomputed from the code
+                    const int m = mlo_[todo] + ((code >> 4) & 31), j = jlo_[todo] + (code & 15);
+                    if (use_tile)
+                        atomicAdd(&tile[(m - mmin) * span_t + (j - jmin)], v);
+                    else
+                        atomicAdd(&grid[(int64_t)m * A.ld + j], v);
                 }
                 // move queued bins to the workspace when the next batch could
                 // overflow the buffer, and at the end of the sub-chunk
@@ -1041,30 +1074,16 @@ __global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
 }
 
 // The queued bins (skipping those of sub-chunks left to k_raster_overflow),
-// in three converged stages per wave: every bin first runs the whole first
-// try of the rejection sampler; the bins it leaves run the fast sampler
-// (from the start: the same tries, up to kFastTries); the bins that leaves
-// (log-scale test) run the full sampler.  Each later stage collects its bins
-// in a wave-local stack and draws them 64 at a time.  A bin's count depends
-// only on its counter, so the stage that draws it does not change it.
+// in two converged stages per wave: every bin first runs the whole first try
+// of the rejection sampler; the bins whose first try was rejected resume the
+// fast sampler at the second try (up to kFastTries), collected in a
+// wave-local stack and drawn 64 at a time.  Bins that reach the log-scale
+// test or use up the fast tries are marked for k_raster_hard.  The full
+// sampler is not compiled in here, so this kernel keeps a small register
+// footprint.  A bin's count depends only on its counter, so the stage that
+// draws it does not change it.
 static constexpr int kDefWaves = 4;
 
-template <int MODE>
-__device__ __forceinline__ void deferred_draw(const RasterItem& one, const RasterItem* items,
-                                              const DeferredBin& db, int stage, float& v) {
-    const RasterItem& I = items ? items[db.item] : one;
-    const RasterArgs& A = I.A;
-    const float q = I.q[db.depo];
-    const double p = (double)db.p;
-    if (stage == 0)
-        v = bin_count_fast<MODE, kStageSecond>(q, p, A.seed, db.depo, A.event, db.bin, A.plane);
-    else if (stage == 1)
-        v = bin_count_fast<MODE, kStageRej>(q, p, A.seed, db.depo, A.event, db.bin, A.plane);
-    else
-        v = bin_count_in<true>(MODE, q, p, A.seed, db.depo, A.event, db.bin, A.plane);
-}
-
-template <int MODE>
 __device__ __forceinline__ void deferred_add(const RasterItem& one, const RasterItem* items,
                                              const DeferredBin& db, float v) {
     const RasterItem& I = items ? items[db.item] : one;
@@ -1072,64 +1091,108 @@ __device__ __forceinline__ void deferred_add(const RasterItem& one, const Raster
     atomicAdd(&I.grid[m * I.A.ld + j], v);
 }
 
+template <int MODE, int STAGE>
+__device__ __forceinline__ float deferred_draw(const RasterItem& one, const RasterItem* items,
+                                               const DeferredBin& db) {
+    const RasterItem& I = items ? items[db.item] : one;
+    const RasterArgs& A = I.A;
+    return bin_count_fast<MODE, STAGE>(I.q[db.depo], (double)db.p, A.seed, db.depo, A.event, db.bin,
+                                       A.plane);
+}
+
+// Marks queue entry idx for k_raster_hard (a plain store to the entry this
+// lane owns: no shared counter, whose atomics would serialise on one
+// address).
+__device__ __forceinline__ void defer_hard(DeferredBin* queue, uint32_t idx) {
+    queue[idx].item |= kHardMark;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
-    RasterItem one, const RasterItem* __restrict__ items, const RasterWs* __restrict__ ws,
-    const uint8_t* __restrict__ flags, const DeferredBin* __restrict__ queue, unsigned long long cap) {
-    __shared__ uint32_t s_stk[kDefWaves][2][128];   // queue indices of stages 1 and 2
+    RasterItem one, const RasterItem* __restrict__ items, RasterWs* __restrict__ ws,
+    const uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue, unsigned long long cap) {
+    __shared__ uint32_t s_stk[kDefWaves][128];   // queue indices of resumed bins
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t* S1 = s_stk[wv][0];
-    uint32_t* S2 = s_stk[wv][1];
+    uint32_t* S1 = s_stk[wv];
     const unsigned long long cnt = min(ws->count, cap);
     const unsigned long long nchunk = (cnt + 63) / 64;
-    int n1 = 0, n2 = 0;   // wave-uniform
+    int n1 = 0;   // wave-uniform
     const uint64_t below = (1ull << lane) - 1;
-    // one batch of 64 (or the rest) from the stage-1 or stage-2 stack
-    auto batch = [&](int stage) {
-        uint32_t* S = stage == 1 ? S1 : S2;
-        int& n = stage == 1 ? n1 : n2;
-        const int c = min(n, 64);
-        bool more = false;
-        uint32_t idx = 0;
-        if (lane < c) {
-            idx = S[n - c + lane];
-            const DeferredBin db = queue[idx];
-            float v;
-            deferred_draw<MODE>(one, items, db, stage, v);
-            if (v != v) more = true;   // stage 1 only: the log-scale test
-            else if (v != 0.f) deferred_add<MODE>(one, items, db, v);
-        }
-        n -= c;
-        if (stage == 1) {
-            const uint64_t mm = __ballot(more);
-            if (more) S2[n2 + __popcll(mm & below)] = idx;
-            n2 += __popcll(mm);
-        }
-    };
-    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;; ch += (unsigned long long)gridDim.x * kDefWaves) {
+    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;;
+         ch += (unsigned long long)gridDim.x * kDefWaves) {
         const bool tail = ch >= nchunk;
-        // drain: stage 2 before stage 1, which pushes into it
-        while (n2 >= 64 || (tail && n2 > 0)) batch(2);
-        while (n1 >= 64 || (tail && n1 > 0)) {
-            batch(1);
-            while (n2 >= 64 || (tail && n2 > 0)) batch(2);
+        while (n1 >= 64 || (tail && n1 > 0)) {   // resumed bins, 64 at a time
+            const int c = min(n1, 64);
+            bool hard = false;
+            uint32_t idx = 0;
+            if (lane < c) {
+                idx = S1[n1 - c + lane];
+                const DeferredBin db = queue[idx];
+                const float v = deferred_draw<MODE, kStageResume>(one, items, db);
+                if (v != v) hard = true;
+                else if (v != 0.f) deferred_add(one, items, db, v);
+            }
+            if (hard) defer_hard(queue, idx);
+            n1 -= c;
         }
         if (tail) break;
         const unsigned long long i = ch * 64 + lane;
-        bool more = false;
+        bool resume = false, hard = false;
         if (i < cnt) {
             const DeferredBin db = queue[i];
             const RasterItem& I = items ? items[db.item] : one;
             if (db.depo != kInvalid && !flags[I.sub_begin + db.depo / kSub]) {
-                float v;
-                deferred_draw<MODE>(one, items, db, 0, v);
-                if (v != v) more = true;
-                else if (v != 0.f) deferred_add<MODE>(one, items, db, v);
+                const float v = deferred_draw<MODE, kStageSecond>(one, items, db);
+                if (v == -__builtin_inff()) resume = true;
+                else if (v != v) hard = true;
+                else if (v != 0.f) deferred_add(one, items, db, v);
             }
         }
-        const uint64_t mm = __ballot(more);
-        if (more) S1[n1 + __popcll(mm & below)] = (uint32_t)i;
+        if (hard) defer_hard(queue, (uint32_t)i);
+        const uint64_t mm = __ballot(resume);
+        if (resume) S1[n1 + __popcll(mm & below)] = (uint32_t)i;
         n1 += __popcll(mm);
+    }
+}
+
+// The bins k_raster_deferred marked: the full rejection samplers.  Each
+// wave scans 64 queue entries at a time, collects the marked ones in a
+// wave-local stack and draws them 64 at a time.
+template <int MODE>
+__global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
+                                                               const RasterItem* __restrict__ items,
+                                                               const RasterWs* __restrict__ ws,
+                                                               const DeferredBin* __restrict__ queue,
+                                                               unsigned long long cap) {
+    __shared__ uint32_t s_stk[kDefWaves][128];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t* S = s_stk[wv];
+    const unsigned long long cnt = min(ws->count, cap);
+    const unsigned long long nchunk = (cnt + 63) / 64;
+    const uint64_t below = (1ull << lane) - 1;
+    int n = 0;   // wave-uniform
+    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;;
+         ch += (unsigned long long)gridDim.x * kDefWaves) {
+        const bool tail = ch >= nchunk;
+        while (n >= 64 || (tail && n > 0)) {
+            const int c = min(n, 64);
+            if (lane < c) {
+                DeferredBin db = queue[S[n - c + lane]];
+                db.item &= ~kHardMark;
+                const RasterItem& I = items ? items[db.item] : one;
+                const RasterArgs& A = I.A;
+                const float v = bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
+                                                   A.event, db.bin, A.plane);
+                if (v != 0.f) deferred_add(one, items, db, v);
+            }
+            n -= c;
+        }
+        if (tail) break;
+        const unsigned long long i = ch * 64 + lane;
+        const bool marked = i < cnt && (queue[i].item & kHardMark) != 0u;
+        const uint64_t mm = __ballot(marked);
+        if (marked) S[n + __popcll(mm & below)] = (uint32_t)i;
+        n += __popcll(mm);
     }
 }
 
@@ -1368,8 +1431,9 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
                        cap);                                                                         \
     if (main_done) (void)hipEventRecord(main_done, s);                                               \
     hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s,  \
-                       one, items,                                                                   \
-                       hdr, flags, queue, cap);                                                      \
+                       one, items, hdr, flags, queue, cap);                                          \
+    hipLaunchKernelGGL(k_raster_hard<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s, one,  \
+                       items, hdr, queue, cap);                                                      \
     hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, one, items, n_items, total_sub,   \
                        flags);                                                                       \
     hipLaunchKernelGGL(k_raster_wide<M>, gw, blk, 0, s, one, items, n_items, total_sub);
