@@ -229,7 +229,7 @@ int lar_batch_destroy(lar_batch *plan);
  *   0: 8s (then one 4 or 2), then 3s   1: 4s, 3s, then one 2
  *   2: 3s, then 8s (then one 4 or 2)  3: the reverse of 0 */
 typedef struct lar_schedule {
-    int32_t row_threads;    /* threads per time-axis row workgroup: 256, 512, 1024 */
+    int32_t row_threads;    /* threads per time-axis row workgroup: 256, 384, 512, 768, 1024 */
     int32_t row_order;      /* radix order of the nt_fft/2-point plan */
     int32_t wire_cols;      /* time-frequency columns per wire-pass tile: 4, 8, 16 */
     int32_t wire_threads;   /* threads per wire-pass workgroup: 256, 512, 1024
@@ -249,8 +249,9 @@ int lar_schedule_get(const lar_plane *plane, lar_schedule *out);
  * 160 KB LDS of a CU.  Thread-safe; calls that overlap a change may launch
  * with either schedule. */
 int lar_schedule_set(const lar_plane *plane, const lar_schedule *sched);
-/* Valid schedules to time: every row choice with the built-in wire pass,
- * then every other wire choice with the built-in rows (radix orders that
+/* Valid schedules to time: the built-in one first, then every other row
+ * choice with the built-in wire pass, then every other wire choice with the
+ * built-in rows (radix orders that
  * repeat an earlier order's plan are left out).  Writes up to cap entries
  * and sets *n to the full count. */
 int lar_schedule_candidates(const lar_plane *plane, lar_schedule *out, int32_t cap, int32_t *n);

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
-    float2* h = lds + lpad_n(Nh);
+    float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
     const TwHalf tw{h, Nh};
     float2 v[VPT];
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int n = tid + i * T;
-            if (n < Nh) A[lpad(n)] = v[i];
+            if (n < Nh) A[n] = v[i];
         }
         // prefetch the next row of this workgroup while this one is transformed
         if (row + (int)gridDim.x < nrows)
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
         // split step: X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2
         float2* y = out + (int64_t)row * ld_out;
         for (int k = tid; k <= Nh / 2; k += T) {
-            float2 zk = A[lpad(k)], zm = A[lpad(k == 0 ? 0 : Nh - k)];
+            float2 zk = A[k], zm = A[k == 0 ? 0 : Nh - k];
             float2 w = h[k];
             float2 e1 = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             float2 d1 = make_float2(zk.x - zm.x, zk.y + zm.y);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
-    float2* h = lds + lpad_n(Nh);
+    float2* h = lds + Nh;
     fill_half_table(h, Nh, tid, T);
     const TwHalf tw{h, Nh};
     // the pre-step touches Nh/2 + 1 bin pairs: VPT/2 (rounded up) per thread
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                 float2 b1 = cmulc(make_float2(xk.x - xm.x, xk.y + xm.y), w);   // * exp(+2 pi i k/Tf)
                 float2 a2 = make_float2(xm.x + xk.x, xm.y - xk.y);
                 float2 b2 = cmul(make_float2(xm.x - xk.x, xm.y + xk.y), make_float2(-w.x, -w.y));
-                A[lpad(k)] = make_float2(a1.x - b1.y, a1.y + b1.x);
-                if (k > 0) A[lpad(Nh - k)] = make_float2(a2.x - b2.y, a2.y + b2.x);
+                A[k] = make_float2(a1.x - b1.y, a1.y + b1.x);
+                if (k > 0) A[Nh - k] = make_float2(a2.x - b2.y, a2.y + b2.x);
             }
         }
         if (row + (int)gridDim.x < nrows)
@@ -201,13 +201,13 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
             float2* y2 = reinterpret_cast<float2*>(y);
             const int full = n_out >> 1;
             for (int n = tid; n < Nh; n += T) {
-                float2 z = A[lpad(n)];
+                float2 z = A[n];
                 if (n < full) y2[n] = make_float2(z.x * scale, z.y * scale);
                 else if (2 * n < n_out) y[2 * n] = z.x * scale;
             }
         } else {
             for (int n = tid; n < Nh; n += T) {
-                float2 z = A[lpad(n)];
+                float2 z = A[n];
                 if (2 * n < n_out) y[2 * n] = z.x * scale;
                 if (2 * n + 1 < n_out) y[2 * n + 1] = z.y * scale;
             }
@@ -243,18 +243,28 @@ int default_row_threads(int nt_fft) {
 
 bool row_sched_ok(int nt_fft, int threads, int order) {
     FftPlan plan;
-    return (threads == 256 || threads == 512 || threads == 1024) && vpt_for(nt_fft / 2, threads) &&
+    return (threads == 256 || threads == 384 || threads == 512 || threads == 768 || threads == 1024) &&
+           vpt_for(nt_fft / 2, threads) &&
            make_plan(nt_fft / 2, &plan, order);
 }
 
-// Instantiations: T in {256, 512, 1024} threads by V in {1, 2, 4, 8} values
-// per thread; f(V, T) is called with the pair that a schedule selects.
+// Instantiations: T in {256, 384, 512, 768, 1024} threads by V in
+// {1, 2, 4, 8} values per thread (384 and 768 hold the 3 * 2^k lengths
+// exactly); f(V, T) is called with the pair that a schedule selects.
 #define LAR_ROW_DISPATCH(V, T, X)                                   \
     switch ((T) * 16 + (V)) {                                       \
         case 256 * 16 + 1: X(1, 256) break;                         \
         case 256 * 16 + 2: X(2, 256) break;                         \
         case 256 * 16 + 4: X(4, 256) break;                         \
         case 256 * 16 + 8: X(8, 256) break;                         \
+        case 384 * 16 + 1: X(1, 384) break;                         \
+        case 384 * 16 + 2: X(2, 384) break;                         \
+        case 384 * 16 + 4: X(4, 384) break;                         \
+        case 384 * 16 + 8: X(8, 384) break;                         \
+        case 768 * 16 + 1: X(1, 768) break;                         \
+        case 768 * 16 + 2: X(2, 768) break;                         \
+        case 768 * 16 + 4: X(4, 768) break;                         \
+        case 768 * 16 + 8: X(8, 768) break;                         \
         case 512 * 16 + 1: X(1, 512) break;                         \
         case 512 * 16 + 2: X(2, 512) break;                         \
         case 512 * 16 + 4: X(4, 512) break;                         \
@@ -277,7 +287,7 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
     const int Nh = plan.n, vpt = vpt_for(Nh, threads);
     if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const size_t lds = ((size_t)lpad_n(Nh) + Nh) * sizeof(float2);
+    const size_t lds = 2 * (size_t)Nh * sizeof(float2);
     const int pairs_ok =
         ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0) ? 1 : 0;
     dim3 grid(row_grid(nrows));
@@ -301,7 +311,7 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
     const int Nh = plan.n, vpt = vpt_for(Nh, threads);
     if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const size_t lds = ((size_t)lpad_n(Nh) + Nh) * sizeof(float2);
+    const size_t lds = 2 * (size_t)Nh * sizeof(float2);
     const int pairs_ok = ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0 &&
                           (row_off == nullptr || row_off_even))
                              ? 1
@@ -341,8 +351,8 @@ void k_wire_fused(
     S += (int64_t)blockIdx.y * strideS;
     M += (int64_t)blockIdx.y * strideM;
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
-    float2* A = lds;               // [Wf][C], padded (lpad)
-    float2* tw = lds + lpad_n(Wf * C);     // [Wf]
+    float2* A = lds;               // [Wf][C]
+    float2* tw = lds + Wf * C;     // [Wf]
     fill_full_table(tw, Wf, tid, T);
     const TwFull twf{tw};
     const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
@@ -391,7 +401,7 @@ void k_wire_fused(
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
-            if (e < nel) A[lpad(e)] = v[i];
+            if (e < nel) A[e] = v[i];
         }
         if (k + 1 < n_imp) gather_s(k + 1);
         lds_barrier();
@@ -400,7 +410,7 @@ void k_wire_fused(
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
             if (e < nel) {
-                float2 a = A[lpad(e)];
+                float2 a = A[e];
                 acc[i].x += a.x * r[i].x - a.y * r[i].y;
                 acc[i].y += a.x * r[i].y + a.y * r[i].x;
             }
@@ -411,7 +421,7 @@ void k_wire_fused(
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         int e = tid + i * T;
-        if (e < nel) A[lpad(e)] = acc[i];
+        if (e < nel) A[e] = acc[i];
     }
     lds_barrier();
     fft_lds<VPT, C>(A, plan, tid, T, twf, true);
@@ -420,7 +430,7 @@ void k_wire_fused(
         int e = tid + i * T;
         if (e < nel) {
             int p = e / C, c = e % C, f = f0 + c;
-            if (p < n_wires && f < F) M[(int64_t)p * ldM + f] = A[lpad(e)];
+            if (p < n_wires && f < F) M[(int64_t)p * ldM + f] = A[e];
         }
     }
 }
@@ -429,7 +439,7 @@ template <int VPT, int C, int NT>
 static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                               const FftPlan& plan, const float2* R, float2* M, int64_t ldM,
                               int batch, int64_t strideS, int64_t strideM, hipStream_t s) {
-    const size_t lds = ((size_t)lpad_n(plan.n * C) + plan.n) * sizeof(float2);
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     set_lds(k_wire_fused<VPT, C, NT>, lds);
     dim3 grid((F + C - 1) / C, batch), block(NT);
     hipLaunchKernelGGL((k_wire_fused<VPT, C, NT>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
@@ -445,7 +455,7 @@ bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
                        (cols == 8 && (threads == 256 || threads == 512 || threads == 1024)) ||
                        (cols == 16 && (threads == 512 || threads == 1024));
     // the tile and its twiddle table must fit the 160 KB of LDS of a CU
-    const size_t lds = ((size_t)lpad_n(nw_fft * cols) + nw_fft) * sizeof(float2);
+    const size_t lds = ((size_t)nw_fft * cols + nw_fft) * sizeof(float2);
     return shape && vpt_for(nw_fft * cols, threads) && lds <= 160 * 1024 &&
            make_plan(nw_fft, &plan, order);
 }
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
     extern __shared__ float2 lds[];
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
-    float2* tw = lds + lpad_n(Wf * C);
+    float2* tw = lds + Wf * C;
     fill_full_table(tw, Wf, tid, T);
     const TwFull twf{tw};
     const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
@@ -521,14 +531,14 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         const int e = tid + i * T;
-        if (e < nel) A[lpad(e)] = gh[i];
+        if (e < nel) A[e] = gh[i];
     }
     lds_barrier();
     fft_lds<VPT, C>(A, plan, tid, T, twf, false);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         const int e = tid + i * T;
-        if (e < nel) gh[i] = A[lpad(e)];
+        if (e < nel) gh[i] = A[e];
     }
     for (int k = 0; k < n_imp; ++k) {
         if (dR) {
@@ -545,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
 #pragma unroll
             for (int i = 0; i < VPT; ++i) {
                 const int e = tid + i * T;
-                if (e < nel) A[lpad(e)] = v[i];
+                if (e < nel) A[e] = v[i];
             }
             lds_barrier();
             fft_lds<VPT, C>(A, plan, tid, T, twf, false);
@@ -556,7 +566,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
                 const int p = e / C, f = f0 + e % C;
                 if (e < nel && f < F) {
                     const float cf = (f == 0 || f == nyq) ? resp_scale : 2.f * resp_scale;
-                    const float2 sk = A[lpad(e)];
+                    const float2 sk = A[e];
                     const float2 g = cmulc(gh[i], sk);   // Gh conj(Sk)
                     float2* o = dRk + (int64_t)p * F + f;
                     float2 cur = *o;
@@ -579,7 +589,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
 #pragma unroll
             for (int i = 0; i < VPT; ++i) {
                 const int e = tid + i * T;
-                if (e < nel) A[lpad(e)] = cmulc(gh[i], r[i]);   // conj(R) Gh
+                if (e < nel) A[e] = cmulc(gh[i], r[i]);   // conj(R) Gh
             }
             lds_barrier();
             fft_lds<VPT, C>(A, plan, tid, T, twf, true);
@@ -587,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
             for (int i = 0; i < VPT; ++i) {
                 const int e = tid + i * T;
                 const int p = e / C, f = f0 + e % C;
-                if (e < nel && p < n_wires && f < F) S[(int64_t)(p * n_imp + k) * ldS + f] = A[lpad(e)];
+                if (e < nel && p < n_wires && f < F) S[(int64_t)(p * n_imp + k) * ldS + f] = A[e];
             }
         }
     }
@@ -597,7 +607,7 @@ template <int VPT, int C, int NT>
 static hipError_t wire_adj_launch(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
                                   int n_imp, int F, int nyq, const FftPlan& plan, const float2* R,
                                   float2* dR, bool want_grid, float scale, hipStream_t s) {
-    const size_t lds = ((size_t)lpad_n(plan.n * C) + plan.n) * sizeof(float2);
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     set_lds(k_wire_adjoint<VPT, C, NT>, lds);
     dim3 grid((F + C - 1) / C), block(NT);
     hipLaunchKernelGGL((k_wire_adjoint<VPT, C, NT>), grid, block, lds, s, Gt, ldG, S, ldS, n_wires,
@@ -636,12 +646,12 @@ __global__ __launch_bounds__(256) void k_wire_spectrum(
     extern __shared__ float2 lds[];
     const int Wf = plan.n, tid = threadIdx.x, T = blockDim.x;
     float2* A = lds;
-    float2* tw = lds + lpad_n(Wf * C);
+    float2* tw = lds + Wf * C;
     fill_full_table(tw, Wf, tid, T);
     const int k = blockIdx.y;
     const int f0 = blockIdx.x * C;
     const int nel = Wf * C;
-    for (int e = tid; e < nel; e += T) A[lpad(e)] = make_float2(0.f, 0.f);
+    for (int e = tid; e < nel; e += T) A[e] = make_float2(0.f, 0.f);
     __syncthreads();
     // rows sharing a wire index are summed by one thread each, in order
     for (int e = tid; e < nel; e += T) {
@@ -653,13 +663,13 @@ __global__ __launch_bounds__(256) void k_wire_spectrum(
             int pi = ((dw % Wf) + Wf) % Wf;
             if (pi == p) a = cadd(a, rows[((int64_t)k * nrw + i) * ld_rows + f]);
         }
-        A[lpad(e)] = a;
+        A[e] = a;
     }
     __syncthreads();
     fft_lds<VPT, C>(A, plan, tid, T, TwFull{tw}, false);
     for (int e = tid; e < nel; e += T) {
         int p = e / C, c = e % C, f = f0 + c;
-        if (f < F) resp[((int64_t)k * Wf + p) * F + f] = A[lpad(e)];
+        if (f < F) resp[((int64_t)k * Wf + p) * F + f] = A[e];
     }
 }
 
@@ -668,7 +678,7 @@ hipError_t launch_wire_spectrum(const float2* rows, int64_t ld_rows, int n_imp, 
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     constexpr int C = 8;
-    const size_t lds = ((size_t)lpad_n(plan.n * C) + plan.n) * sizeof(float2);
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     dim3 grid((F + C - 1) / C, n_imp), block(256);
     if (nw_fft * C <= 8 * 256) {
         set_lds(k_wire_spectrum<8, C>, lds);

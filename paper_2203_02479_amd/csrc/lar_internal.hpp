@@ -118,26 +118,16 @@ struct TwFull {           // table of n entries
 struct TwHalf {           // table h[k] = exp(-pi i k / n), k < n (half-angle table)
     const float2* t;
     int n;
-    __device__ __forceinline__ float2 operator()(int m) const {
-        int i = 2 * m;
-        if (i < n) return t[i];
-        float2 v = t[i - n];
-        return make_float2(-v.x, -v.y);
+    __device__ __forceinline__ float2 operator()(int m) const {   // branch-free
+        const int i = 2 * m;
+        const bool hi = i >= n;
+        const float2 v = t[hi ? i - n : i];
+        return hi ? make_float2(-v.x, -v.y) : v;
     }
 };
 
-// Padded LDS index of element i of a transform buffer: one unused slot
-// after every 16 complex elements.  The first Stockham passes write with a
-// stride of R (or R*NS) elements, a power of two that would put a
-// half-wave's 64-bit stores on a few of the 32 banks (12-way conflicts for
-// R = 8); the padding spreads them over all banks.
-constexpr int kPadShift = 4;
-__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> kPadShift); }
-// Elements a padded buffer of n elements occupies.
-__host__ __device__ __forceinline__ int lpad_n(int n) { return n + (n >> kPadShift) + 1; }
-
 // One Stockham pass over NS interleaved sequences held in LDS (element i of
-// sequence s at A[lpad(i*NS + s)]).  All loads of a thread happen before the
+// sequence s at A[i*NS + s]).  All loads of a thread happen before the
 // barrier and all stores after it, so the pass is in place.
 template <int R, int MAXB, int NS, class TW>
 __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid, int T,
@@ -145,6 +135,9 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
     const int nb = n / R;
     const int total = nb * NS;
     const int stride = n / (Ns * R);
+    // Ns is a power of two in every pass before the first radix-3 one
+    // (wave-uniform test): a mask then replaces the integer remainder
+    const bool ns_pow2 = (Ns & (Ns - 1)) == 0;
     float2 v[MAXB][R];
     int dst[MAXB];
 #pragma unroll
@@ -153,10 +146,10 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
         dst[b] = -1;
         if (w < total) {
             int s = w % NS, j = w / NS;
-            int k = j % Ns;
+            int k = ns_pow2 ? (j & (Ns - 1)) : j % Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 x = A[lpad((j + r * nb) * NS + s)];
+                float2 x = A[(j + r * nb) * NS + s];
                 if (r > 0) {
                     float2 t = tw(r * k * stride);
                     x = inv ? cmulc(x, t) : cmul(x, t);
@@ -172,7 +165,7 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
         if (dst[b] >= 0) {
             dft_small<R>(v[b], inv);
 #pragma unroll
-            for (int r = 0; r < R; ++r) A[lpad(dst[b] + r * Ns * NS)] = v[b][r];
+            for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * NS] = v[b][r];
         }
     }
     lds_barrier();

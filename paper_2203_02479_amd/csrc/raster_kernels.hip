@@ -24,6 +24,15 @@
 
 namespace lar {
 
+// Float add to the grid in global memory.  The grid pointer arrives in a
+// struct (a generic pointer), so the address space is stated here: a global
+// atomic instead of a flat one.
+typedef __attribute__((address_space(1))) float global_float;
+__device__ __forceinline__ void grid_add(float* p, float v) {
+    __hip_atomic_fetch_add((global_float*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- Philox
 
 struct PhiloxStream {
@@ -900,7 +909,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                         for (int a = r0; a < anx; a += step) trow[a * span_t] += qwt * w[kMaxT + a];
                     } else {
                         for (int a = r0; a < anx; a += step)
-                            atomicAdd(&grid[(int64_t)(m0 + a) * A.ld + j], qwt * w[kMaxT + a]);
+                            grid_add(&grid[(int64_t)(m0 + a) * A.ld + j], qwt * w[kMaxT + a]);
                     }
                 }
                 // other lanes touch these cells for the next depo: keep program order
@@ -931,89 +940,6 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             int nq = 0;                 // wave-uniform queue size
             int d = 0;
             int c0 = 0;
-            // one batch of 64 (or the rest) from stack st
-            auto batch = [&](const int st) {   // st is wave-uniform
-                wave_lds_sync();
-                const int cnt = min(nL[st], 64);
-                int todo = -1, code = 0;
-                bool defer = false, move = false;
-                float v = 0.f;
-                if (lane < cnt) {
-                    code = L0[st * 128 + nL[st] - cnt + lane];
-                    const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
-                    const float* w = W + dd * kSlot;
-                    const int j = jlo_[dd] + b;
-                    const int m = mlo_[dd] + a;
-                    const double p = (double)(w[b] * w[kMaxT + a]);
-                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                    const uint32_t dg = (uint32_t)(base + dd);
-                    if (st == kStkZ)
-                        v = bin_count_fast<MODE, kStageZero>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
-                    else if (st == kStkF)
-                        v = bin_count_fast<MODE, kStageFirst>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
-                    else
-                        v = bin_count_fast<MODE, kStageInv>(q_[dd], p, A.seed, dg, A.event, bin, A.plane,
-                                                            s_rcp);
-                    if (v != v) {
-                        if (st == kStkF) defer = true;
-                        else move = true;
-                    } else if (v != 0.f) {
-                        todo = dd;
-                    }
-                }
-                nL[st] -= cnt;
-                const uint64_t below = (1ull << lane) - 1;
-                if (st == kStkZ) {   // failed zero tests go to the low-mean inversion stack
-                    const uint64_t mm = __ballot(move);
-                    if (move) L0[kStkI * 128 + nL[kStkI] + __popcll(mm & below)] = (uint16_t)code;
-                    nL[kStkI] += __popcll(mm);
-                }
-                if (st == kStkF) {
-                    const uint64_t dm = __ballot(defer);
-                    if (defer) s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)code;
-                    nq += __popcll(dm);
-                }
-                // add the drawn counts: two depos of one batch may share a cell,
-                // so the tile takes LDS atomics here (cheaper than serialising
-                // the lanes by depo, measured)
-                if (todo >= 0) {   // the cell, recomputed from the code
-                    const int m = mlo_[todo] + ((code >> 4) & 31), j = jlo_[todo] + (code & 15);
-                    if (use_tile)
-                        atomicAdd(&tile[(m - mmin) * span_t + (j - jmin)], v);
-                    else
-                        atomicAdd(&grid[(int64_t)m * A.ld + j], v);
-                }
-                // move queued bins to the workspace when the next batch could
-                // overflow the buffer, and at the end of the sub-chunk
-                const bool last = c0 >= total && nL[0] == 0 && nL[1] == 0 && nL[2] == 0 && nL[3] == 0;
-                if (nq > kWaveQueue - 64 || (last && nq > 0)) {
-                    wave_lds_sync();
-                    unsigned long long gb = 0;
-                    if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
-                    gb = __shfl(gb, 0, 64);
-                    const bool fits = gb + (unsigned long long)nq <= cap;
-                    for (int e = lane; e < nq; e += 64) {
-                        const unsigned long long slot = gb + (unsigned long long)e;
-                        if (slot >= cap) continue;
-                        DeferredBin db;
-                        db.item = (uint32_t)it;
-                        if (fits) {
-                            const int cd = s_queue[wv][e];
-                            const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
-                            const float* w = W + dq * kSlot;
-                            db.depo = (uint32_t)(base + dq);
-                            db.bin = (uint32_t)((int64_t)(mlo_[dq] + a) * A.n_ticks + (jlo_[dq] + b));
-                            db.p = w[b] * w[kMaxT + a];
-                        } else {
-                            db.depo = kInvalid; db.bin = 0; db.p = 0.f;
-                        }
-                        queue[slot] = db;
-                    }
-                    if (!fits && lane == 0) flags[gsub] = 1;
-                    nq = 0;
-                    wave_lds_sync();
-                }
-            };
             for (;;) {
                 const bool tail = c0 >= total;
                 const int thr = tail ? 1 : 64;
@@ -1022,8 +948,87 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                                : nL[kStkZ] >= thr ? kStkZ
                                : nL[kStkF] >= thr ? kStkF
                                                   : -1;
-                if (st >= 0) {
-                    batch(st);
+                if (st >= 0) {   // one batch of 64 (or the rest) from stack st (wave-uniform)
+                    wave_lds_sync();
+                    const int cnt = min(nL[st], 64);
+                    int todo = -1, code = 0;
+                    bool defer = false, move = false;
+                    float v = 0.f;
+                    if (lane < cnt) {
+                        code = L0[st * 128 + nL[st] - cnt + lane];
+                        const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
+                        const float* w = W + dd * kSlot;
+                        const int j = jlo_[dd] + b;
+                        const int m = mlo_[dd] + a;
+                        const double p = (double)(w[b] * w[kMaxT + a]);
+                        const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                        const uint32_t dg = (uint32_t)(base + dd);
+                        if (st == kStkZ)
+                            v = bin_count_fast<MODE, kStageZero>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                        else if (st == kStkF)
+                            v = bin_count_fast<MODE, kStageFirst>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                        else
+                            v = bin_count_fast<MODE, kStageInv>(q_[dd], p, A.seed, dg, A.event, bin, A.plane,
+                                                                s_rcp);
+                        if (v != v) {
+                            if (st == kStkF) defer = true;
+                            else move = true;
+                        } else if (v != 0.f) {
+                            todo = dd;
+                        }
+                    }
+                    nL[st] -= cnt;
+                    const uint64_t below = (1ull << lane) - 1;
+                    if (st == kStkZ) {   // failed zero tests go to the low-mean inversion stack
+                        const uint64_t mm = __ballot(move);
+                        if (move) L0[kStkI * 128 + nL[kStkI] + __popcll(mm & below)] = (uint16_t)code;
+                        nL[kStkI] += __popcll(mm);
+                    }
+                    if (st == kStkF) {
+                        const uint64_t dm = __ballot(defer);
+                        if (defer) s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)code;
+                        nq += __popcll(dm);
+                    }
+                    // add the drawn counts: two depos of one batch may share a cell,
+                    // so the tile takes LDS atomics here (cheaper than serialising
+                    // the lanes by depo, measured)
+                    if (todo >= 0) {   // the cell, recomputed from the code
+                        const int m = mlo_[todo] + ((code >> 4) & 31), j = jlo_[todo] + (code & 15);
+                        if (use_tile)
+                            atomicAdd(&tile[(m - mmin) * span_t + (j - jmin)], v);
+                        else
+                            grid_add(&grid[(int64_t)m * A.ld + j], v);
+                    }
+                    // move queued bins to the workspace when the next batch could
+                    // overflow the buffer, and at the end of the sub-chunk
+                    const bool last = c0 >= total && nL[0] == 0 && nL[1] == 0 && nL[2] == 0 && nL[3] == 0;
+                    if (nq > kWaveQueue - 64 || (last && nq > 0)) {
+                        wave_lds_sync();
+                        unsigned long long gb = 0;
+                        if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
+                        gb = __shfl(gb, 0, 64);
+                        const bool fits = gb + (unsigned long long)nq <= cap;
+                        for (int e = lane; e < nq; e += 64) {
+                            const unsigned long long slot = gb + (unsigned long long)e;
+                            if (slot >= cap) continue;
+                            DeferredBin db;
+                            db.item = (uint32_t)it;
+                            if (fits) {
+                                const int cd = s_queue[wv][e];
+                                const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                                const float* w = W + dq * kSlot;
+                                db.depo = (uint32_t)(base + dq);
+                                db.bin = (uint32_t)((int64_t)(mlo_[dq] + a) * A.n_ticks + (jlo_[dq] + b));
+                                db.p = w[b] * w[kMaxT + a];
+                            } else {
+                                db.depo = kInvalid; db.bin = 0; db.p = 0.f;
+                            }
+                            queue[slot] = db;
+                        }
+                        if (!fits && lane == 0) flags[gsub] = 1;
+                        nq = 0;
+                        wave_lds_sync();
+                    }
                     continue;
                 }
                 if (tail) break;
@@ -1058,7 +1063,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                 float v = tile[e];
                 if (v != 0.f) {
                     int r = e / span_t, ci = e - r * span_t;
-                    atomicAdd(&grid[(int64_t)(mmin + r) * A.ld + jmin + ci], v);
+                    grid_add(&grid[(int64_t)(mmin + r) * A.ld + jmin + ci], v);
                     tile[e] = 0.f;
                 }
             }
@@ -1088,7 +1093,7 @@ __device__ __forceinline__ void deferred_add(const RasterItem& one, const Raster
                                              const DeferredBin& db, float v) {
     const RasterItem& I = items ? items[db.item] : one;
     const int64_t m = db.bin / (uint32_t)I.A.n_ticks, j = db.bin - m * I.A.n_ticks;
-    atomicAdd(&I.grid[m * I.A.ld + j], v);
+    grid_add(&I.grid[m * I.A.ld + j], v);
 }
 
 template <int MODE, int STAGE>
@@ -1230,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const R
                 float v = bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                 if (v != v) {   // queued by k_raster: draw it here
                     v = bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                    if (v != 0.f) atomicAdd(&I.grid[(int64_t)m * A.ld + j], v);
+                    if (v != 0.f) grid_add(&I.grid[(int64_t)m * A.ld + j], v);
                 }
             }
         }
@@ -1292,7 +1297,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterItem one,
                     const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
                     v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                 }
-                if (v != 0.f) atomicAdd(&I.grid[(int64_t)m * A.ld + j], v);
+                if (v != 0.f) grid_add(&I.grid[(int64_t)m * A.ld + j], v);
             }
         }
         __syncthreads();

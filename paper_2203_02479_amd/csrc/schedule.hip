@@ -132,25 +132,33 @@ int lar_schedule_candidates(const lar_plane* p, lar_schedule* out, int32_t cap, 
     int st;
     if ((st = check_shape(p))) return st;
     if (!n || cap < 0 || (cap > 0 && !out)) return LAR_EINVAL;
+    static const int row_threads[5] = {256, 384, 512, 768, 1024};
     static const int threads[3] = {256, 512, 1024};
     static const int cols[3] = {4, 8, 16};
     const Sched d = sched_default(p->nt_fft, p->nw_fft);
     int count = 0;
+    auto same = [](const Sched& a, const Sched& b) {
+        return a.row_threads == b.row_threads && a.row_order == b.row_order &&
+               a.wire_cols == b.wire_cols && a.wire_threads == b.wire_threads &&
+               a.wire_order == b.wire_order;
+    };
     auto emit = [&](const Sched& s) {
         if (!sched_ok(s, p->nt_fft, p->nw_fft)) return;
         if (count < cap) to_abi(s, out + count);
         ++count;
     };
+    emit(d);   // the built-in schedule first
+
     // row choices with the default wire pass, then wire choices with the
     // default rows: the two stages are timed apart, so the candidate list is
     // their union rather than their product
-    for (int t : threads)
+    for (int t : row_threads)
         for (int o = 0; o < kPlanOrders; ++o) {
             if (order_repeats(p->nt_fft / 2, o)) continue;
             Sched s = d;
             s.row_threads = t;
             s.row_order = o;
-            emit(s);
+            if (!same(s, d)) emit(s);
         }
     for (int c : cols)
         for (int t : threads)
@@ -160,11 +168,7 @@ int lar_schedule_candidates(const lar_plane* p, lar_schedule* out, int32_t cap, 
                 s.wire_cols = c;
                 s.wire_threads = t;
                 s.wire_order = o;
-                if (s.row_threads == d.row_threads && s.row_order == d.row_order &&
-                    s.wire_cols == d.wire_cols && s.wire_threads == d.wire_threads &&
-                    s.wire_order == d.wire_order)
-                    continue;   // the default is already listed
-                emit(s);
+                if (!same(s, d)) emit(s);
             }
     *n = count;
     return LAR_OK;
