@@ -229,7 +229,9 @@ __device__ __forceinline__ int btrd_ratio_accept(double v, double k, double m, d
 }
 
 // Binomial by BTRD, transformed rejection with decomposition (p <= 1/2, n p >= 10).
-__device__ double binom_btrd(double n, double p, PhiloxStream& s) {
+// from: the first try to run, with the stream at Philox block `from` (every
+// earlier try went past its immediate acceptance and took one block).
+__device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0) {
 #pragma clang fp contract(off)
     // constants of the fast acceptance region first; those of the slow
     // path are formed only when it is reached (identical values)
@@ -242,7 +244,7 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s) {
     double urvr = 0.86 * vr;
     double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
     bool slow_ready = false;
-    for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = from; tries < LAR_MAX_TRIES; ++tries) {
         double v = next_uniform(s);
         double u;
         if (v <= urvr) {
@@ -311,7 +313,7 @@ __device__ double poisson_inversion(double lam, PhiloxStream& s) {
 }
 
 // Poisson by PTRS, transformed rejection with squeeze (lam >= 10).
-__device__ double poisson_ptrs(double lam, PhiloxStream& s) {
+__device__ double poisson_ptrs(double lam, PhiloxStream& s, int from = 0) {   // from as for binom_btrd
 #pragma clang fp contract(off)
     double slam = sqrt(lam);
     double loglam = log(lam);
@@ -319,7 +321,7 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s) {
     double a = -0.059 + 0.02483 * b;
     double invalpha = 1.1239 + 1.1328 / (b - 3.4);
     double vr = 0.9277 - 3.6224 / (b - 2.0);
-    for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = from; tries < LAR_MAX_TRIES; ++tries) {
         double u = next_uniform(s) - 0.5;
         double v = next_uniform(s);
         double us = 0.5 - fabs(u);
@@ -340,14 +342,16 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s) {
 // counter and reaches the same result.  TRIES limits the tries: with
 // kTryAccept only the first try's immediate-acceptance region is taken (-1
 // otherwise), with 1 the whole first try: cheap stages that most bins finish
-// in, run apart so that a wave's lanes stay converged.  Returns -1 when a try
-// needs the log-scale test, -2 when TRIES tries were rejected.
+// in, run apart so that a wave's lanes stay converged.  Returns -1 - t when
+// try t needs the log-scale test, kTriesUsed when every try up to TRIES was
+// rejected.
 //
 // A try that is not accepted at once takes exactly two uniforms, one Philox
 // block, so try t >= 1 starts at block t when every earlier try went past
 // its immediate acceptance: binom_btrd_fast_from resumes the sampler there.
 static constexpr int kFastTries = 4;
 static constexpr int kTryAccept = 0;
+static constexpr double kTriesUsed = -100.0;
 
 template <int TRIES>
 __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStream& s, int from = 0) {
@@ -388,10 +392,10 @@ __device__ __forceinline__ double binom_btrd_fast(double n, double p, PhiloxStre
         if (k < 0.0 || k > n) continue;
         v = v * alpha / (a / (us * us) + b);
         double km = fabs(k - m);
-        if (km > 15.0) return -1.0;
+        if (km > 15.0) return -1.0 - tries;
         if (btrd_ratio_accept(v, k, m, nr, r)) return k;
     }
-    return -2.0;
+    return kTriesUsed;
 }
 
 // PTRS without its logarithmic acceptance test (same tries and decisions as
@@ -414,9 +418,9 @@ __device__ __forceinline__ double poisson_ptrs_fast(double lam, PhiloxStream& s,
         if (us >= 0.07 && v <= vr) return k;
         if (TRIES == kTryAccept) return -1.0;
         if (k < 0.0 || (us < 0.013 && v > us)) continue;
-        return -1.0;
+        return -1.0 - tries;
     }
-    return -2.0;
+    return kTriesUsed;
 }
 
 // The opening test of the inversion samplers for a small mean (n p < 1,
@@ -453,15 +457,22 @@ __device__ __forceinline__ double poisson_zero_test(double lam, PhiloxStream& s)
 //                acceptance and was rejected: the fast rejection sampler
 //                from the second try (stream at block 1)
 //   kStageAll    any bin: inversion or the fast rejection sampler by regime
-// Undecided bins return NaN, or -infinity for kStageSecond when the first
-// try was rejected (the bin can resume; NaN there means the log-scale test).
+// Undecided bins return NaN.  For the rejection stages, *next (when given)
+// then holds where the draw continues: the try t that needs the log-scale
+// test (encoded t), or, when every try of the stage was rejected, the next
+// try for the fast sampler (encoded kNextFast + t).
 enum { kStageZero = 0, kStageInv = 1, kStageFirst = 2, kStageRej = 3, kStageAll = 4, kStageSecond = 5,
        kStageResume = 6 };
+static constexpr int kNextFast = 16;
+
+__device__ __forceinline__ int next_try(double code, int tries_of_stage) {
+    return code == kTriesUsed ? kNextFast + tries_of_stage : (int)(-1.0 - code);
+}
 
 template <int MODE, int STAGE>
 __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
                                                 uint32_t event, uint32_t bin, uint32_t plane,
-                                                const double* rtab = nullptr) {
+                                                const double* rtab = nullptr, int* next = nullptr) {
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
@@ -496,8 +507,10 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
                 k = binom_inversion(n, pp, s, rtab);
             else
                 k = (n * pp < kInvMean) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast<kFastTries>(n, pp, s);
-            if (STAGE == kStageSecond && k == -2.0) return -__builtin_inff();
-            if (k < 0.0) return __builtin_nanf("");
+            if (k < 0.0) {
+                if (next) *next = next_try(k, STAGE == kStageSecond ? 1 : kFastTries);
+                return __builtin_nanf("");
+            }
             r = flip ? n - k : k;
         }
     } else {
@@ -519,8 +532,10 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
                 r = poisson_inversion(lam, s);
             else
                 r = (lam < kInvMean) ? poisson_inversion(lam, s) : poisson_ptrs_fast<kFastTries>(lam, s);
-            if (STAGE == kStageSecond && r == -2.0) return -__builtin_inff();
-            if (r < 0.0) return __builtin_nanf("");
+            if (r < 0.0) {
+                if (next) *next = next_try(r, STAGE == kStageSecond ? 1 : kFastTries);
+                return __builtin_nanf("");
+            }
         }
     }
     float f = (float)r;
@@ -569,13 +584,16 @@ __device__ __forceinline__ int sampler_stack(int mode, float q, double p) {
 }
 
 // Signed count of one bin, for a bin known to be in the given regime.
+// from > 0 (rejection regime only): resume at try `from`, every earlier try
+// having gone past its immediate acceptance (one Philox block each).
 template <bool REJECT>
 __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint64_t seed,
                                               uint32_t depo, uint32_t event, uint32_t bin,
-                                              uint32_t plane) {
+                                              uint32_t plane, int from = 0) {
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
+    s.c3 += (uint32_t)from;
     double aq = fabs((double)q);
     double r;
     if (mode == 1) {
@@ -587,12 +605,12 @@ __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint6
         } else {
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
-            double k = REJECT ? binom_btrd(n, pp, s) : binom_inversion(n, pp, s, nullptr);
+            double k = REJECT ? binom_btrd(n, pp, s, from) : binom_inversion(n, pp, s, nullptr);
             r = flip ? n - k : k;
         }
     } else {
         double lam = aq * p;
-        r = !(lam > 0.0) ? 0.0 : (REJECT ? poisson_ptrs(lam, s) : poisson_inversion(lam, s));
+        r = !(lam > 0.0) ? 0.0 : (REJECT ? poisson_ptrs(lam, s, from) : poisson_inversion(lam, s));
     }
     float f = (float)r;
     return q < 0.f ? -f : f;
@@ -1098,18 +1116,19 @@ __device__ __forceinline__ void deferred_add(const RasterItem& one, const Raster
 
 template <int MODE, int STAGE>
 __device__ __forceinline__ float deferred_draw(const RasterItem& one, const RasterItem* items,
-                                               const DeferredBin& db) {
+                                               const DeferredBin& db, int* next) {
     const RasterItem& I = items ? items[db.item] : one;
     const RasterArgs& A = I.A;
     return bin_count_fast<MODE, STAGE>(I.q[db.depo], (double)db.p, A.seed, db.depo, A.event, db.bin,
-                                       A.plane);
+                                       A.plane, nullptr, next);
 }
 
-// Marks queue entry idx for k_raster_hard (a plain store to the entry this
-// lane owns: no shared counter, whose atomics would serialise on one
-// address).
-__device__ __forceinline__ void defer_hard(DeferredBin* queue, uint32_t idx) {
-    queue[idx].item |= kHardMark;
+// Marks queue entry idx for k_raster_hard, which resumes the full sampler at
+// try t (a plain store to the entry this lane owns: no shared counter, whose
+// atomics would serialise on one address).
+static constexpr uint32_t kHardTryShift = 28;   // DeferredBin::item bits 28-30: t
+__device__ __forceinline__ void defer_hard(DeferredBin* queue, uint32_t idx, int t) {
+    queue[idx].item |= kHardMark | ((uint32_t)t << kHardTryShift);
 }
 
 template <int MODE>
@@ -1128,41 +1147,42 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
         const bool tail = ch >= nchunk;
         while (n1 >= 64 || (tail && n1 > 0)) {   // resumed bins, 64 at a time
             const int c = min(n1, 64);
-            bool hard = false;
-            uint32_t idx = 0;
             if (lane < c) {
-                idx = S1[n1 - c + lane];
+                const uint32_t idx = S1[n1 - c + lane];
                 const DeferredBin db = queue[idx];
-                const float v = deferred_draw<MODE, kStageResume>(one, items, db);
-                if (v != v) hard = true;
+                int next = 0;
+                const float v = deferred_draw<MODE, kStageResume>(one, items, db, &next);
+                if (v != v) defer_hard(queue, idx, next >= kNextFast ? next - kNextFast : next);
                 else if (v != 0.f) deferred_add(one, items, db, v);
             }
-            if (hard) defer_hard(queue, idx);
             n1 -= c;
         }
         if (tail) break;
         const unsigned long long i = ch * 64 + lane;
-        bool resume = false, hard = false;
+        bool resume = false;
         if (i < cnt) {
             const DeferredBin db = queue[i];
             const RasterItem& I = items ? items[db.item] : one;
             if (db.depo != kInvalid && !flags[I.sub_begin + db.depo / kSub]) {
-                const float v = deferred_draw<MODE, kStageSecond>(one, items, db);
-                if (v == -__builtin_inff()) resume = true;
-                else if (v != v) hard = true;
-                else if (v != 0.f) deferred_add(one, items, db, v);
+                int next = 0;
+                const float v = deferred_draw<MODE, kStageSecond>(one, items, db, &next);
+                if (v != v) {
+                    if (next >= kNextFast) resume = true;      // first try rejected
+                    else defer_hard(queue, (uint32_t)i, next);  // log-scale test
+                } else if (v != 0.f) {
+                    deferred_add(one, items, db, v);
+                }
             }
         }
-        if (hard) defer_hard(queue, (uint32_t)i);
         const uint64_t mm = __ballot(resume);
         if (resume) S1[n1 + __popcll(mm & below)] = (uint32_t)i;
         n1 += __popcll(mm);
     }
 }
 
-// The bins k_raster_deferred marked: the full rejection samplers.  Each
-// wave scans 64 queue entries at a time, collects the marked ones in a
-// wave-local stack and draws them 64 at a time.
+// The bins k_raster_deferred marked: the full rejection samplers, resumed at
+// the marked try.  Each wave scans 64 queue entries at a time, collects the
+// marked ones in a wave-local stack and draws them 64 at a time.
 template <int MODE>
 __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
                                                                const RasterItem* __restrict__ items,
@@ -1183,11 +1203,12 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
             const int c = min(n, 64);
             if (lane < c) {
                 DeferredBin db = queue[S[n - c + lane]];
-                db.item &= ~kHardMark;
+                const int from = (int)((db.item >> kHardTryShift) & 7u);
+                db.item &= (1u << kHardTryShift) - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
                 const RasterArgs& A = I.A;
                 const float v = bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
-                                                   A.event, db.bin, A.plane);
+                                                   A.event, db.bin, A.plane, from);
                 if (v != 0.f) deferred_add(one, items, db, v);
             }
             n -= c;
