@@ -200,7 +200,7 @@ typedef struct lar_batch lar_batch;    /* opaque plan */
 
 /* Workspace for a plan: item and row tables, every item's grid, time
  * spectra and wire-pass output, and the raster queue (fluct only).
- * n_items < 2^28 (LAR_ESIZE otherwise). */
+ * n_items < 2^27 (LAR_ESIZE otherwise). */
 int lar_batch_workspace(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
                         int32_t n_items, const lar_fluct *fluct, size_t *bytes);
 

@@ -57,7 +57,7 @@ struct Layout {
 int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
            const lar_fluct* fluct, Layout& L) {
     if (!planes || n_types < 1 || !items || n_items < 1) return LAR_EINVAL;
-    if (n_items >= (1 << 28)) return LAR_ESIZE;   // item index shares a 32-bit word with queue marks
+    if (n_items >= (1 << 27)) return LAR_ESIZE;   // item index shares a 32-bit word with queue marks
     if (fluct && (fluct->mode < 0 || fluct->mode > 2)) return LAR_EINVAL;
     for (int t = 0; t < n_types; ++t)
         if (!plane_ok(planes[t])) return LAR_ESIZE;

@@ -165,6 +165,11 @@ __device__ __forceinline__ double ipow_n(double x, double n) {
 // uniform is compared with a lower bound of f(0) first: (1-p)^n >= 1 - n p
 // (Bernoulli), minus a margin above the rounding of q and of the powering,
 // so the early return of 0 happens only where the full test returns 0.
+// ONE_TRY: return -1 instead of redrawing when the search runs off its end
+// (k = n or k > 110 reached with u left over): the stream is then not needed
+// past the first uniform, which keeps the hot kernel's registers down; the
+// caller redraws the bin with the full sampler.
+template <bool ONE_TRY = false>
 __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStream& s,
                                                   const double* rtab) {
 #pragma clang fp contract(off)
@@ -175,7 +180,7 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
     double np = n * p;
     if (np < 1.0 && u < (1.0 - np) - (n + 64.0) * 8.8817841970012523e-16) return 0.0;
     double f0 = ipow_n(q, n);
-    for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = 0; tries < (ONE_TRY ? 1 : LAR_MAX_TRIES); ++tries) {
         if (tries > 0) u = next_uniform(s);
         double f = f0;
         double k = 0.0;
@@ -202,7 +207,7 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
             }
         }
     }
-    return floor(n * p);
+    return ONE_TRY ? -1.0 : floor(n * p);
 }
 
 // BTRD's explicit test v <= f(k)/f(m) for |k - m| <= 15, with the pmf ratio
@@ -293,12 +298,14 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0) 
 // Poisson by inversion (0 < lam < 10).  For lam < 1 the first uniform is
 // compared with exp(-lam) >= 1 - lam (minus a margin above exp's rounding)
 // first, which decides k = 0 exactly where the full test does.
+// ONE_TRY as for binom_inversion.
+template <bool ONE_TRY = false>
 __device__ double poisson_inversion(double lam, PhiloxStream& s) {
 #pragma clang fp contract(off)
     double u = next_uniform(s);
     if (lam < 1.0 && u < (1.0 - lam) - 1e-13) return 0.0;
     double p0 = exp(-lam);
-    for (int tries = 0; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = 0; tries < (ONE_TRY ? 1 : LAR_MAX_TRIES); ++tries) {
         if (tries > 0) u = next_uniform(s);
         double p = p0, cdf = p0, k = 0.0;
         while (u > cdf) {
@@ -309,7 +316,7 @@ __device__ double poisson_inversion(double lam, PhiloxStream& s) {
         }
         if (u <= cdf) return k;
     }
-    return floor(lam);
+    return ONE_TRY ? -1.0 : floor(lam);
 }
 
 // Poisson by PTRS, transformed rejection with squeeze (lam >= 10).
@@ -504,7 +511,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
             else if (STAGE == kStageRej)
                 k = binom_btrd_fast<kFastTries>(n, pp, s);
             else if (STAGE == kStageInv)
-                k = binom_inversion(n, pp, s, rtab);
+                k = binom_inversion<true>(n, pp, s, rtab);
             else
                 k = (n * pp < kInvMean) ? binom_inversion(n, pp, s, rtab) : binom_btrd_fast<kFastTries>(n, pp, s);
             if (k < 0.0) {
@@ -529,7 +536,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
             else if (STAGE == kStageRej)
                 r = poisson_ptrs_fast<kFastTries>(lam, s);
             else if (STAGE == kStageInv)
-                r = poisson_inversion(lam, s);
+                r = poisson_inversion<true>(lam, s);
             else
                 r = (lam < kInvMean) ? poisson_inversion(lam, s) : poisson_ptrs_fast<kFastTries>(lam, s);
             if (r < 0.0) {
@@ -747,7 +754,7 @@ static constexpr int kSub = 16;           // depos per wave sub-chunk
 static constexpr int kMaxT = 16;          // window limits of the LDS slots (bins)
 static constexpr int kMaxX = 32;
 static constexpr int kSlot = kMaxT + kMaxX + 1;
-static constexpr int kWaveTile = 1024;    // floats of a wave's private tile
+static constexpr int kWaveTile = 512;     // floats of a wave's private tile
 static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
 static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
@@ -765,6 +772,7 @@ struct RasterWs {
     unsigned long long count;    // bins queued (may exceed the capacity)
 };
 static constexpr uint32_t kHardMark = 0x80000000u;   // DeferredBin::item bit: left to k_raster_hard
+static constexpr uint32_t kInvMark = 0x08000000u;    // ... an inversion bin (else a rejection one)
 
 int64_t raster_subchunks(int64_t n) { return (n + kSub - 1) / kSub; }
 
@@ -805,8 +813,10 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// 5 waves per SIMD: the sampler stages fit 96 VGPRs, and the LDS of a
+// workgroup (about 29 KB) lets 5 workgroups share a CU
 template <int MODE>
-__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(5, 8)))
 void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items, int64_t total_sub,
               RasterWs* __restrict__ ws, uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue,
               unsigned long long cap) {
@@ -988,9 +998,9 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                         else
                             v = bin_count_fast<MODE, kStageInv>(q_[dd], p, A.seed, dg, A.event, bin, A.plane,
                                                                 s_rcp);
-                        if (v != v) {
-                            if (st == kStkF) defer = true;
-                            else move = true;
+                        if (v != v) {   // Z: to I; I, J (search ran off its end) and F: queued
+                            if (st == kStkZ) move = true;
+                            else defer = true;
                         } else if (v != 0.f) {
                             todo = dd;
                         }
@@ -1002,9 +1012,11 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                         if (move) L0[kStkI * 128 + nL[kStkI] + __popcll(mm & below)] = (uint16_t)code;
                         nL[kStkI] += __popcll(mm);
                     }
-                    if (st == kStkF) {
+                    if (st != kStkZ) {
                         const uint64_t dm = __ballot(defer);
-                        if (defer) s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)code;
+                        // bit 13 of a queued code: an inversion bin (full inversion in k_raster_hard)
+                        if (defer)
+                            s_queue[wv][nq + __popcll(dm & below)] = (uint16_t)(code | (st != kStkF ? 8192 : 0));
                         nq += __popcll(dm);
                     }
                     // add the drawn counts: two depos of one batch may share a cell,
@@ -1033,7 +1045,8 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                             db.item = (uint32_t)it;
                             if (fits) {
                                 const int cd = s_queue[wv][e];
-                                const int dq = cd >> 9, a = (cd >> 4) & 31, b = cd & 15;
+                                const int dq = (cd >> 9) & 15, a = (cd >> 4) & 31, b = cd & 15;
+                                if (cd & 8192) db.item |= kHardMark | kInvMark;
                                 const float* w = W + dq * kSlot;
                                 db.depo = (uint32_t)(base + dq);
                                 db.bin = (uint32_t)((int64_t)(mlo_[dq] + a) * A.n_ticks + (jlo_[dq] + b));
@@ -1162,8 +1175,8 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
         bool resume = false;
         if (i < cnt) {
             const DeferredBin db = queue[i];
-            const RasterItem& I = items ? items[db.item] : one;
-            if (db.depo != kInvalid && !flags[I.sub_begin + db.depo / kSub]) {
+            const RasterItem& I = items ? items[db.item & (kInvMark - 1u)] : one;
+            if (db.depo != kInvalid && !(db.item & kHardMark) && !flags[I.sub_begin + db.depo / kSub]) {
                 int next = 0;
                 const float v = deferred_draw<MODE, kStageSecond>(one, items, db, &next);
                 if (v != v) {
@@ -1204,11 +1217,14 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
             if (lane < c) {
                 DeferredBin db = queue[S[n - c + lane]];
                 const int from = (int)((db.item >> kHardTryShift) & 7u);
-                db.item &= (1u << kHardTryShift) - 1u;
+                const bool inv = (db.item & kInvMark) != 0u;
+                db.item &= kInvMark - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
                 const RasterArgs& A = I.A;
-                const float v = bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
-                                                   A.event, db.bin, A.plane, from);
+                const float v = inv ? bin_count_in<false>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
+                                                          A.event, db.bin, A.plane)
+                                    : bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
+                                                         A.event, db.bin, A.plane, from);
                 if (v != 0.f) deferred_add(one, items, db, v);
             }
             n -= c;
@@ -1224,8 +1240,8 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
 
 // Sub-chunks whose deferred bins did not fit in the queue: recompute their
 // regular depos' bins and draw the deferred ones (rejection-regime bins
-// that the first try's immediate acceptance did not decide) with the full
-// samplers.
+// that the first try's immediate acceptance did not decide, inversion bins
+// whose search ran off its end) with the full samplers.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const RasterItem* __restrict__ items,
                                                          int n_items, int64_t total_sub,
@@ -1252,10 +1268,14 @@ __global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const R
                 const int j = wt.lo + b, m = wx.lo + a;
                 const double p = (double)(wtv * wxv);
                 const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                if (sampler_stack(MODE, q, p) != kStkF) continue;
-                float v = bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                if (v != v) {   // queued by k_raster: draw it here
-                    v = bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                // queued by k_raster: rejection bins the first stage left, and
+                // inversion bins (Z, I, J) whose one-try search ran off its end
+                const bool rej = sampler_stack(MODE, q, p) == kStkF;
+                float v = rej ? bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane)
+                              : bin_count_fast<MODE, kStageInv>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                if (v != v) {   // draw it here
+                    v = rej ? bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane)
+                            : bin_count_in<false>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
                     if (v != 0.f) grid_add(&I.grid[(int64_t)m * A.ld + j], v);
                 }
             }
