@@ -81,6 +81,24 @@ def count_bins(P, dep, nsigma):
     return int(np.sum(np.where(ok, nt * nx, 0)))
 
 
+def load_traffic(path):
+    """Measured HBM bytes per launch of each stage's kernel (rocprofv3
+    FETCH_SIZE / WRITE_SIZE, scaled by a plain copy's reading), kept only for
+    stages whose kernel sources are unchanged since the counters were taken."""
+    from paper_2203_02479_amd import profsum
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return {}
+    out = {}
+    for stage, rec in data.items():
+        if stage.startswith("_") or not isinstance(rec, dict):
+            continue
+        if rec.get("source") == profsum.source_digest(stage):
+            out[stage] = rec["bytes"]
+    return out
+
+
 def copy_calibration(torch):
     """A plain copy kernel of known size (an elementwise multiply by one: reads
     1 GiB, writes 1 GiB), for scaling the PMC byte counters."""
@@ -289,12 +307,7 @@ def main():
         return
 
     P, dep, r, seed, n_depo, ms, per, host_s = leg_forward(args, torch, lar, inputs, np)
-    traffic = {}
-    if os.path.exists(args.traffic):
-        try:
-            traffic = json.load(open(args.traffic))
-        except Exception:
-            traffic = {}
+    traffic = load_traffic(args.traffic)
     nbytes = algorithmic_bytes(P)
     bins = count_bins(P, dep, inputs.NSIGMA)
     dom = max(per, key=per.get)

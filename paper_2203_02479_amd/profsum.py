@@ -31,6 +31,25 @@ STAGE_KERNELS = {
     "c2r": r"k_c2r_rows",
 }
 CALIB_BYTES = 4 * (1 << 28)          # bench.py --calib copies 1 GiB of float32
+# source files each stage's kernels are built from: a stored traffic figure
+# holds only while their contents are unchanged
+STAGE_SOURCES = {
+    "fill": ("fft_kernels.hip", "lar_internal.hpp"),
+    "raster": ("raster_kernels.hip", "lar_internal.hpp"),
+    "r2c": ("fft_kernels.hip", "lar_internal.hpp"),
+    "wire": ("fft_kernels.hip", "lar_internal.hpp"),
+    "c2r": ("fft_kernels.hip", "lar_internal.hpp"),
+}
+
+
+def source_digest(stage):
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in STAGE_SOURCES[stage]:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _find(d, suffix):
@@ -106,7 +125,7 @@ def traffic(fd, wd, cfd, cwd):
         rd = f[k] * 1024.0 * kf
         wr = w.get(k, 0.0) * 1024.0 * kw
         out[stage] = {"kernel": k, "read_bytes": round(rd), "write_bytes": round(wr),
-                      "bytes": round(rd + wr)}
+                      "bytes": round(rd + wr), "source": source_digest(stage)}
     return out
 
 
