@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--skip-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT schedules")
     ap.add_argument("--calib", action="store_true", help="run the copy-kernel counter calibration only")
+    ap.add_argument("--leg", choices=["fwd_bwd", "batched"], default=None,
+                    help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per kernel launch (rocprofv3 FETCH/WRITE_SIZE), if present")
     args = ap.parse_args()
@@ -304,6 +306,10 @@ def main():
     torch.cuda.set_device(0)
     if args.calib:
         copy_calibration(torch)
+        return
+    if args.leg:
+        leg = leg_fwd_bwd if args.leg == "fwd_bwd" else leg_batched
+        print(json.dumps({args.leg: leg(args, torch, lar, inputs, np)}), flush=True)
         return
 
     P, dep, r, seed, n_depo, ms, per, host_s = leg_forward(args, torch, lar, inputs, np)

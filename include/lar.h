@@ -149,6 +149,21 @@ int lar_fftconv_backward(const lar_plane *plane, const float *grid, const float 
                          const float *wave_grad, float *grid_grad, float *resp_grad,
                          void *workspace, size_t ws_bytes, void *stream);
 
+/* lar_fftconv_backward with the grid given by its time spectrum: after
+ * lar_fftconv returns, its workspace begins with grid_spec, the real FFT
+ * over ticks of every grid row, [n_wires*n_imp][ld] complex64 (float
+ * pairs), ld = nt_fft/2 + 1 rounded up to a multiple of 16.  Keeping that
+ * workspace for the backward pass saves the transform of the grid.
+ * grid_spec is overwritten (it holds the grid-gradient spectrum) when
+ * grid_grad is given.  resp_accumulate != 0: resp_grad += gradient, as in
+ * lar_fftconv_backward; 0: resp_grad = gradient.  Workspace: the FT of
+ * wave_grad (lar_fftconv_backward_spec_workspace). */
+int lar_fftconv_backward_spec_workspace(const lar_plane *plane, size_t *bytes);
+int lar_fftconv_backward_spec(const lar_plane *plane, void *grid_spec, const float *resp,
+                              const float *wave_grad, float *grid_grad, float *resp_grad,
+                              int32_t resp_accumulate, void *workspace, size_t ws_bytes,
+                              void *stream);
+
 /* Adjoint of the mean raster (no paper counterpart): for every depo the
  * gradient of L = sum grid_grad * S with respect to q, t, x, sigma_t,
  * sigma_x, windows held fixed (the patch is recomputed, not stored):

@@ -1,10 +1,12 @@
 """Differentiable plane simulation: a torch.autograd.Function over the C ABI.
 
 Forward: mean raster (no fluctuation) + FFT convolution -> waveforms.
-Backward: lar_fftconv_backward (grid and response-spectrum gradients), then
-lar_raster_backward (depo gradients), which recomputes each depo's patch
-instead of storing it.  The grid S is kept from the forward pass (it is
-needed for the response-spectrum gradient).
+Backward: lar_fftconv_backward_spec (grid and response-spectrum gradients)
+from the grid's time spectrum, which the forward convolution leaves at the
+start of its workspace and which is kept instead of the grid (it is what the
+response-spectrum gradient needs, and keeping it saves transforming the grid
+again); then lar_raster_backward (depo gradients), which recomputes each
+depo's patch instead of storing it.
 
 Gradient convention for the response spectrum: resp is a float32 tensor
 [n_imp][nw_fft][nt_fft/2+1][2] of (re, im) pairs and its gradient holds
@@ -27,21 +29,23 @@ class SimPlaneFunction(torch.autograd.Function):
         ws = lar.workspace(lar.fftconv_workspace(plane), q.device)
         resp_c = resp.detach().contiguous()
         lar.fftconv(plane, grid, resp_c, wave, ws)
-        ctx.save_for_backward(D.q, D.t, D.x, D.sigma_t, D.sigma_x, resp_c, grid)
+        del grid
+        ctx.save_for_backward(D.q, D.t, D.x, D.sigma_t, D.sigma_x, resp_c, ws)   # ws: grid spectrum
         ctx.plane, ctx.nsigma = plane, nsigma
         return wave
 
     @staticmethod
     def backward(ctx, gwave):
-        q, t, x, st, sx, resp, grid = ctx.saved_tensors
+        q, t, x, st, sx, resp, spec = ctx.saved_tensors
         plane, nsigma = ctx.plane, ctx.nsigma
         need_depo = any(ctx.needs_input_grad[:5])
         need_resp = ctx.needs_input_grad[5]
-        grid_grad = torch.empty_like(grid) if need_depo else None
-        resp_grad = torch.zeros_like(resp) if need_resp else None
-        ws = lar.workspace(lar.fftconv_backward_workspace(plane), gwave.device)
-        lar.fftconv_backward(plane, grid if need_resp else None, resp, gwave.contiguous(), grid_grad,
-                             resp_grad, ws)
+        dev = gwave.device
+        grid_grad = (torch.empty((plane.n_wires * plane.n_imp, plane.n_ticks), dtype=torch.float32, device=dev)
+                     if need_depo else None)
+        resp_grad = torch.empty_like(resp) if need_resp else None      # overwritten
+        ws = lar.workspace(lar.fftconv_backward_spec_workspace(plane), dev)
+        lar.fftconv_backward_spec(plane, spec, resp, gwave.contiguous(), grid_grad, resp_grad, ws)
         grads = [None] * 5
         if need_depo:
             grads = [torch.empty_like(q) for _ in range(5)]

@@ -301,6 +301,48 @@ int lar_fftconv_backward(const lar_plane* p, const float* grid, const float* res
     return LAR_OK;
 }
 
+// backward from a kept grid spectrum: workspace = the FT of wave_grad only
+static size_t fftconv_bwd_spec_bytes(const lar_plane* p) {
+    return align_up((size_t)p->n_wires * (size_t)spec_ld(p) * sizeof(float2), 256);
+}
+
+int lar_fftconv_backward_spec_workspace(const lar_plane* plane, size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = fftconv_bwd_spec_bytes(plane);
+    return LAR_OK;
+}
+
+int lar_fftconv_backward_spec(const lar_plane* p, void* grid_spec, const float* resp,
+                              const float* wave_grad, float* grid_grad, float* resp_grad,
+                              int32_t resp_accumulate, void* ws, size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(p))) return st;
+    if (!resp || !wave_grad) return LAR_EINVAL;
+    if (!grid_grad && !resp_grad) return LAR_OK;
+    if (!grid_spec) return LAR_EINVAL;
+    if (!ws || ws_bytes < fftconv_bwd_spec_bytes(p) || reinterpret_cast<uintptr_t>(ws) % 256)
+        return LAR_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ld = spec_ld(p);
+    const int rows = p->n_wires * p->n_imp;
+    float2* Gt = reinterpret_cast<float2*>(ws);
+    float2* Sb = reinterpret_cast<float2*>(grid_spec);
+    const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
+    const Sched sc = sched_of(p);
+    LAR_TRY(launch_r2c_rows(wave_grad, p->n_ticks, p->n_ticks, p->n_wires, p->nt_fft, Gt, ld, s,
+                            sc.row_threads, sc.row_order));
+    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
+                                reinterpret_cast<const float2*>(resp),
+                                reinterpret_cast<float2*>(resp_grad), grid_grad != nullptr, scale, s,
+                                resp_accumulate != 0));
+    if (grid_grad)
+        LAR_TRY(launch_c2r_rows(Sb, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s,
+                                nullptr, false, sc.row_threads, sc.row_order));
+    return LAR_OK;
+}
+
 int lar_raster_backward(const lar_plane* plane, const lar_depos* depos, float nsigma,
                         const float* grid_grad, float* dq, float* dt, float* dx, float* dsigma_t,
                         float* dsigma_x, void* stream) {

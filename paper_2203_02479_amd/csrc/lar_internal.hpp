@@ -273,9 +273,10 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
 hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);
+// accumulate: dR += the gradient (else dR = the gradient).
 hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
                                int n_imp, int nw_fft, int nt_fft, const float2* R, float2* dR,
-                               bool want_grid, float resp_scale, hipStream_t s);
+                               bool want_grid, float resp_scale, hipStream_t s, bool accumulate = true);
 hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
                                 const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                                 hipStream_t s);

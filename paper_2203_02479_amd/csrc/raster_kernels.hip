@@ -183,27 +183,30 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
     for (int tries = 0; tries < (ONE_TRY ? 1 : LAR_MAX_TRIES); ++tries) {
         if (tries > 0) u = next_uniform(s);
         double f = f0;
-        double k = 0.0;
+        // the search stops past k = n or k = 110 (n is a whole number): an
+        // integer bound, and an integer step counter
+        const int kmax = n < 111.0 ? (int)n : 111;
+        int k = 0;
         if (rtab) {
             // 1/k correctly rounded, from the table (kRcpTable entries); the
             // next step's entry is loaded one step ahead
             double ik_next = rtab[1];
-            for (int ki = 1;; ++ki) {
-                if (u < f) return k;
-                if (k >= n || k > 110.0) break;
+            for (;;) {
+                if (u < f) return (double)k;
+                if (k >= kmax) break;
                 u = u - f;
-                k = k + 1.0;
+                ++k;
                 const double ik = ik_next;
-                ik_next = rtab[ki + 1];
+                ik_next = rtab[k + 1];
                 f = f * (g * ik - ratio);
             }
         } else {
             for (;;) {
-                if (u < f) return k;
-                if (k >= n || k > 110.0) break;
+                if (u < f) return (double)k;
+                if (k >= kmax) break;
                 u = u - f;
-                k = k + 1.0;
-                f = f * (g * (1.0 / k) - ratio);
+                ++k;
+                f = f * (g * (1.0 / (double)k) - ratio);
             }
         }
     }

@@ -77,6 +77,9 @@ SIGNATURES = {
                               ctypes.c_int),
     "lar_fftconv_backward_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
     "lar_fftconv_backward": ([_P(lar_plane), _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
+    "lar_fftconv_backward_spec_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_fftconv_backward_spec": ([_P(lar_plane), _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _SZ, _VP],
+                                  ctypes.c_int),
     "lar_raster_backward": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
                             ctypes.c_int),
     "lar_batch_workspace": ([_P(lar_plane), ctypes.c_int32, _P(lar_batch_item), ctypes.c_int32, _P(lar_fluct),
@@ -236,6 +239,29 @@ def fftconv_backward(plane, grid, resp, wave_grad, grid_grad, resp_grad, ws, str
     _check(_lib().lar_fftconv_backward(ctypes.byref(pl), _ptr(grid), _ptr(resp), _ptr(wave_grad),
                                        _ptr(grid_grad), _ptr(resp_grad), _ptr(ws), ws.numel(),
                                        _stream(stream)), "lar_fftconv_backward")
+
+
+def fftconv_backward_spec_workspace(plane) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_fftconv_backward_spec_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)),
+           "lar_fftconv_backward_spec_workspace")
+    return n.value
+
+
+def spectrum_ld(plane) -> int:
+    """Row pitch (complex elements) of the grid spectrum lar_fftconv leaves at
+    the start of its workspace."""
+    return (plane.nt_fft // 2 + 1 + 15) // 16 * 16
+
+
+def fftconv_backward_spec(plane, grid_spec, resp, wave_grad, grid_grad, resp_grad, ws, accumulate=False,
+                          stream=None):
+    """grid_spec: a device buffer holding the grid spectrum (e.g. the fftconv
+    workspace after lar_fftconv); overwritten when grid_grad is given."""
+    pl = make_plane(plane)
+    _check(_lib().lar_fftconv_backward_spec(ctypes.byref(pl), _ptr(grid_spec), _ptr(resp), _ptr(wave_grad),
+                                            _ptr(grid_grad), _ptr(resp_grad), 1 if accumulate else 0, _ptr(ws),
+                                            ws.numel(), _stream(stream)), "lar_fftconv_backward_spec")
 
 
 def raster_backward(plane, depos: DeviceDepos, nsigma, grid_grad, dq, dt, dx, dsigma_t, dsigma_x,

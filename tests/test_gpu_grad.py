@@ -50,6 +50,33 @@ def test_fftconv_backward_vs_oracle(case):
     assert torch.equal(gg2, gg)
 
 
+@pytest.mark.parametrize("case", [dict(n_wires=5, n_ticks=40, n_imp=2, nt_fft=48, nw_fft=9),
+                                  dict(n_wires=30, n_ticks=6000, n_imp=10, nt_fft=6144, nw_fft=512)])
+def test_fftconv_backward_from_kept_spectrum(case):
+    """The backward pass from the spectrum lar_fftconv leaves in its
+    workspace: same gradients as the oracle; resp_grad overwritten or
+    accumulated as asked."""
+    torch, lar = _t()
+    P = inputs.Plane(**case)
+    S = inputs.random_grid(P, 5, density=0.3)
+    R = inputs.random_spectrum(P, 6)
+    G = np.random.default_rng(7).standard_normal((P.n_wires, P.n_ticks)).astype(np.float32)
+    cu = lambda a: torch.as_tensor(a).cuda().contiguous()
+    GS, dR = oracle.conv_adjoint(P, S, R, G)
+    for accumulate in (False, True):
+        ws = lar.workspace(lar.fftconv_workspace(P))
+        wave = torch.empty((P.n_wires, P.n_ticks), device="cuda")
+        lar.fftconv(P, cu(S), cu(R), wave, ws)            # leaves the grid spectrum in ws
+        gg = torch.full((P.n_rows, P.n_ticks), float("nan"), device="cuda")
+        rg = torch.full(R.shape, 3.0 if accumulate else float("nan"), device="cuda")
+        wsb = lar.workspace(lar.fftconv_backward_spec_workspace(P))
+        lar.fftconv_backward_spec(P, ws, cu(R), cu(G), gg, rg, wsb, accumulate=accumulate)
+        torch.cuda.synchronize()
+        assert rel_l2(gg.cpu().numpy(), GS) < RTOL_GRAD
+        got = rg.cpu().numpy() - (3.0 if accumulate else 0.0)
+        assert rel_l2(got[..., 0] + 1j * got[..., 1], dR) < RTOL_GRAD
+
+
 @pytest.mark.parametrize("kind", ["cfg0", "random"])
 def test_raster_backward_vs_oracle(kind):
     torch, lar = _t()
