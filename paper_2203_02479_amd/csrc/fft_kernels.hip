@@ -73,30 +73,33 @@ __device__ __forceinline__ void fill_half_table(float2* h, int Nh, int tid, int 
     }
 }
 
-// Even/odd sample pairs of one row into registers: pair n = tid + i*T.
-// Loads are unconditional (addresses clamped into the row) so that the
-// whole row is in flight at once.
+// Even/odd sample pairs of one row into registers, pair n = tid + i*T, in
+// two halves: issue_row_pairs only issues the loads (unconditional, with
+// addresses clamped into the row), and row_pair masks a loaded pair when it
+// is stored to LDS.  Nothing reads the loaded registers in between, so the
+// next row's loads stay in flight across the current row's transform (a
+// select right after the loads would make the compiler wait for them before
+// the transform).  pairs_ok (n_in even, 8-byte aligned rows): one 8-byte
+// load per pair; else two 4-byte loads.
 template <int VPT>
-__device__ __forceinline__ void load_row_pairs(const float* __restrict__ x, int n_in, int Nh,
-                                               int tid, int T, bool pairs_ok, float2 (&v)[VPT]) {
+__device__ __forceinline__ void issue_row_pairs(const float* __restrict__ x, int n_in, int tid, int T,
+                                                bool pairs_ok, float2 (&raw)[VPT]) {
     if (pairs_ok) {
         const float2* x2 = reinterpret_cast<const float2*>(x);
-        const int full = n_in >> 1;
+        const int last = (n_in >> 1) - 1;
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            int n = tid + i * T;
-            float2 a = x2[min(n, max(full - 1, 0))];
-            float tail = x[min(2 * n, n_in - 1)];
-            v[i] = n < full ? a : make_float2(2 * n < n_in ? tail : 0.f, 0.f);
-        }
+        for (int i = 0; i < VPT; ++i) raw[i] = x2[min(tid + i * T, last)];
     } else {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            int n = tid + i * T;
-            float a = x[min(2 * n, n_in - 1)], b = x[min(2 * n + 1, n_in - 1)];
-            v[i] = make_float2(2 * n < n_in ? a : 0.f, 2 * n + 1 < n_in ? b : 0.f);
+            const int n = tid + i * T;
+            raw[i] = make_float2(x[min(2 * n, n_in - 1)], x[min(2 * n + 1, n_in - 1)]);
         }
     }
+}
+
+__device__ __forceinline__ float2 row_pair(float2 raw, int n, int n_in) {
+    return make_float2(2 * n < n_in ? raw.x : 0.f, 2 * n + 1 < n_in ? raw.y : 0.f);
 }
 
 template <int VPT, int NT>
@@ -112,17 +115,17 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
     const TwHalf tw{h, Nh};
     float2 v[VPT];
     int row = blockIdx.x;
-    if (row < nrows) load_row_pairs<VPT>(in + (int64_t)row * ld_in, n_in, Nh, tid, T, pairs_ok, v);
+    if (row < nrows) issue_row_pairs<VPT>(in + (int64_t)row * ld_in, n_in, tid, T, pairs_ok != 0, v);
     for (; row < nrows; row += gridDim.x) {
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int n = tid + i * T;
-            if (n < Nh) A[n] = v[i];
+            if (n < Nh) A[n] = row_pair(v[i], n, n_in);
         }
         // prefetch the next row of this workgroup while this one is transformed
         if (row + (int)gridDim.x < nrows)
-            load_row_pairs<VPT>(in + (int64_t)(row + gridDim.x) * ld_in, n_in, Nh, tid, T, pairs_ok, v);
+            issue_row_pairs<VPT>(in + (int64_t)(row + gridDim.x) * ld_in, n_in, tid, T, pairs_ok != 0, v);
         lds_barrier();
         fft_lds<VPT, 1>(A, plan, tid, T, tw, false);
         // split step: X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2
@@ -375,14 +378,15 @@ void k_wire_fused(
     static_assert(NT % C == 0, "tile width must divide the thread count");
     const int c_own = tid % C, p_own = tid / C, f_own = min(f0 + c_own, F - 1);
     const bool f_ok = f0 + c_own < F;
+    // (the rows are loaded raw and masked only when stored to LDS: a select
+    // right after the loads would make the compiler wait for them before the
+    // FFT they are meant to overlap)
     auto gather_s = [&](int k) {
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int p = p_own + i * (NT / C);
             asm volatile("" : "+v"(p));
-            bool ok = f_ok && p < n_wires;   // n_wires <= Wf
-            float2 x = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + f_own];
-            v[i] = ok ? x : make_float2(0.f, 0.f);
+            v[i] = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + f_own];
         }
     };
     auto gather_r = [&](int k) {
@@ -401,7 +405,8 @@ void k_wire_fused(
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
-            if (e < nel) A[e] = v[i];
+            const bool ok = f_ok && p_own + i * (NT / C) < n_wires;   // n_wires <= Wf
+            if (e < nel) A[e] = ok ? v[i] : make_float2(0.f, 0.f);
         }
         if (k + 1 < n_imp) gather_s(k + 1);
         lds_barrier();
