@@ -218,28 +218,30 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
 // the product of the i's (no division).
 __device__ __forceinline__ int btrd_ratio_accept(double v, double k, double m, double nr, double r) {
 #pragma clang fp contract(off)
+    // one loop over i in (min(k, m), max(k, m)], ascending, for either
+    // order of k and m (the same products as two separate loops, without
+    // running both when a wave holds lanes of each case)
+    const bool up = m < k;
+    const double lo = (up ? m : k) + 1.0;
+    const int steps = (int)fabs(k - m);
     double num = 1.0, den = 1.0;
-    if (m < k) {
-        for (double i = m + 1.0; i <= k; i = i + 1.0) {
-            num = num * (nr - r * i);
-            den = den * i;
-        }
-        return v * den <= num;
+    for (int t = 0; t < steps; ++t) {
+        const double i = lo + (double)t;
+        num = num * (nr - r * i);
+        den = den * i;
     }
-    if (m > k) {
-        for (double i = k + 1.0; i <= m; i = i + 1.0) {
-            num = num * (nr - r * i);
-            den = den * i;
-        }
-        return v * num <= den;
-    }
+    if (up) return v * den <= num;
+    if (m > k) return v * num <= den;
     return v <= 1.0;
 }
 
 // Binomial by BTRD, transformed rejection with decomposition (p <= 1/2, n p >= 10).
 // from: the first try to run, with the stream at Philox block `from` (every
 // earlier try went past its immediate acceptance and took one block).
-__device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0) {
+// to < LAR_MAX_TRIES: run tries [from, to) only and return -1 if none of
+// them accepts (the draw then continues at try `to`).
+__device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0,
+                             int to = LAR_MAX_TRIES) {
 #pragma clang fp contract(off)
     // constants of the fast acceptance region first; those of the slow
     // path are formed only when it is reached (identical values)
@@ -252,7 +254,7 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0) 
     double urvr = 0.86 * vr;
     double m = 0.0, r = 0.0, nr = 0.0, alpha = 0.0;
     bool slow_ready = false;
-    for (int tries = from; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = from; tries < to; ++tries) {
         double v = next_uniform(s);
         double u;
         if (v <= urvr) {
@@ -294,6 +296,7 @@ __device__ double binom_btrd(double n, double p, PhiloxStream& s, int from = 0) 
                       - stirling_tail(k) - stirling_tail(n - k))
             return k;
     }
+    if (to < LAR_MAX_TRIES) return -1.0;
     if (!slow_ready) m = floor((n + 1.0) * p);
     return m;
 }
@@ -323,7 +326,8 @@ __device__ double poisson_inversion(double lam, PhiloxStream& s) {
 }
 
 // Poisson by PTRS, transformed rejection with squeeze (lam >= 10).
-__device__ double poisson_ptrs(double lam, PhiloxStream& s, int from = 0) {   // from as for binom_btrd
+__device__ double poisson_ptrs(double lam, PhiloxStream& s, int from = 0,   // from, to as for binom_btrd
+                               int to = LAR_MAX_TRIES) {
 #pragma clang fp contract(off)
     double slam = sqrt(lam);
     double loglam = log(lam);
@@ -331,7 +335,7 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s, int from = 0) {   //
     double a = -0.059 + 0.02483 * b;
     double invalpha = 1.1239 + 1.1328 / (b - 3.4);
     double vr = 0.9277 - 3.6224 / (b - 2.0);
-    for (int tries = from; tries < LAR_MAX_TRIES; ++tries) {
+    for (int tries = from; tries < to; ++tries) {
         double u = next_uniform(s) - 0.5;
         double v = next_uniform(s);
         double us = 0.5 - fabs(u);
@@ -341,7 +345,7 @@ __device__ double poisson_ptrs(double lam, PhiloxStream& s, int from = 0) {   //
         if (log(v) + log(invalpha) - log(a / (us * us) + b) <= -lam + k * loglam - lgamma(k + 1.0))
             return k;
     }
-    return floor(lam);
+    return to < LAR_MAX_TRIES ? -1.0 : floor(lam);
 }
 
 // BTRD without its logarithmic acceptance test: the same tries, the same
@@ -596,10 +600,11 @@ __device__ __forceinline__ int sampler_stack(int mode, float q, double p) {
 // Signed count of one bin, for a bin known to be in the given regime.
 // from > 0 (rejection regime only): resume at try `from`, every earlier try
 // having gone past its immediate acceptance (one Philox block each).
+// to (rejection regime): stop after try to - 1, NaN if no try accepted.
 template <bool REJECT>
 __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint64_t seed,
                                               uint32_t depo, uint32_t event, uint32_t bin,
-                                              uint32_t plane, int from = 0) {
+                                              uint32_t plane, int from = 0, int to = LAR_MAX_TRIES) {
 #pragma clang fp contract(off)
     PhiloxStream s;
     stream_init(s, seed, depo, event, bin, plane);
@@ -615,12 +620,14 @@ __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint6
         } else {
             bool flip = p > 0.5;
             double pp = flip ? 1.0 - p : p;
-            double k = REJECT ? binom_btrd(n, pp, s, from) : binom_inversion(n, pp, s, nullptr);
+            double k = REJECT ? binom_btrd(n, pp, s, from, to) : binom_inversion(n, pp, s, nullptr);
+            if (k < 0.0) return __builtin_nanf("");
             r = flip ? n - k : k;
         }
     } else {
         double lam = aq * p;
-        r = !(lam > 0.0) ? 0.0 : (REJECT ? poisson_ptrs(lam, s, from) : poisson_inversion(lam, s));
+        r = !(lam > 0.0) ? 0.0 : (REJECT ? poisson_ptrs(lam, s, from, to) : poisson_inversion(lam, s));
+        if (r < 0.0) return __builtin_nanf("");
     }
     float f = (float)r;
     return q < 0.f ? -f : f;
@@ -1148,7 +1155,8 @@ __device__ __forceinline__ void defer_hard(DeferredBin* queue, uint32_t idx, int
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
+__global__ __launch_bounds__(kDefWaves * 64) __attribute__((amdgpu_waves_per_eu(5, 8)))
+void k_raster_deferred(
     RasterItem one, const RasterItem* __restrict__ items, RasterWs* __restrict__ ws,
     const uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue, unsigned long long cap) {
     __shared__ uint32_t s_stk[kDefWaves][128];   // queue indices of resumed bins
@@ -1162,6 +1170,7 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
          ch += (unsigned long long)gridDim.x * kDefWaves) {
         const bool tail = ch >= nchunk;
         while (n1 >= 64 || (tail && n1 > 0)) {   // resumed bins, 64 at a time
+            wave_lds_sync();   // stack entries written by other lanes
             const int c = min(n1, 64);
             if (lane < c) {
                 const uint32_t idx = S1[n1 - c + lane];
@@ -1196,48 +1205,88 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_deferred(
     }
 }
 
-// The bins k_raster_deferred marked: the full rejection samplers, resumed at
-// the marked try.  Each wave scans 64 queue entries at a time, collects the
-// marked ones in a wave-local stack and draws them 64 at a time.
+// The bins k_raster_deferred marked: the full rejection samplers, one try
+// per pass, from the marked try.  Each wave scans 64 queue entries at a
+// time and collects the marked ones in a wave-local stack; a batch of 64
+// runs one full try of each (log-scale test included), and a bin whose try
+// is rejected goes back on the stack with the next try.  The scan reads
+// kScan chunks at a time so that their loads overlap.  (Running each bin
+// to its end in one pass kept a wave busy for the longest lane's several
+// tries.)  Inversion bins (queued by k_raster) take the full inversion.
 template <int MODE>
 __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
                                                                const RasterItem* __restrict__ items,
                                                                const RasterWs* __restrict__ ws,
                                                                const DeferredBin* __restrict__ queue,
                                                                unsigned long long cap) {
-    __shared__ uint32_t s_stk[kDefWaves][128];
+    constexpr int kScan = 4;                 // chunks of 64 entries scanned per step
+    __shared__ uint32_t s_idx[kDefWaves][64 * (kScan + 2)];
+    __shared__ uint16_t s_try[kDefWaves][64 * (kScan + 2)];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t* S = s_stk[wv];
+    uint32_t* SI = s_idx[wv];
+    uint16_t* ST = s_try[wv];
     const unsigned long long cnt = min(ws->count, cap);
     const unsigned long long nchunk = (cnt + 63) / 64;
     const uint64_t below = (1ull << lane) - 1;
     int n = 0;   // wave-uniform
-    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;;
-         ch += (unsigned long long)gridDim.x * kDefWaves) {
+    unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;
+    for (;;) {
         const bool tail = ch >= nchunk;
-        while (n >= 64 || (tail && n > 0)) {
+        if (n >= 64 || (tail && n > 0)) {
+            wave_lds_sync();
             const int c = min(n, 64);
+            bool again = false;
+            uint32_t idx = 0;
+            int t = 0;
             if (lane < c) {
-                DeferredBin db = queue[S[n - c + lane]];
-                const int from = (int)((db.item >> kHardTryShift) & 7u);
+                idx = SI[n - c + lane];
+                t = ST[n - c + lane];
+                DeferredBin db = queue[idx];
                 const bool inv = (db.item & kInvMark) != 0u;
                 db.item &= kInvMark - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
                 const RasterArgs& A = I.A;
-                const float v = inv ? bin_count_in<false>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
-                                                          A.event, db.bin, A.plane)
-                                    : bin_count_in<true>(MODE, I.q[db.depo], (double)db.p, A.seed, db.depo,
-                                                         A.event, db.bin, A.plane, from);
-                if (v != 0.f) deferred_add(one, items, db, v);
+                const float q = I.q[db.depo];
+                const float v = inv ? bin_count_in<false>(MODE, q, (double)db.p, A.seed, db.depo, A.event,
+                                                          db.bin, A.plane)
+                                    : bin_count_in<true>(MODE, q, (double)db.p, A.seed, db.depo, A.event,
+                                                         db.bin, A.plane, t, t + 1);
+                if (v != v) again = true;
+                else if (v != 0.f) deferred_add(one, items, db, v);
             }
             n -= c;
+            const uint64_t mm = __ballot(again);
+            if (again) {
+                const int slot = n + __popcll(mm & below);
+                SI[slot] = idx;
+                ST[slot] = (uint16_t)(t + 1);
+            }
+            n += __popcll(mm);
+            continue;
         }
         if (tail) break;
-        const unsigned long long i = ch * 64 + lane;
-        const bool marked = i < cnt && (queue[i].item & kHardMark) != 0u;
-        const uint64_t mm = __ballot(marked);
-        if (marked) S[n + __popcll(mm & below)] = (uint32_t)i;
-        n += __popcll(mm);
+        // scan kScan chunks (their loads in flight together); n < 64 here,
+        // so up to 64 * kScan more entries fit
+        const unsigned long long G = (unsigned long long)gridDim.x * kDefWaves;
+        uint32_t item[kScan];
+#pragma unroll
+        for (int u = 0; u < kScan; ++u) {
+            const unsigned long long i = (ch + u * G) * 64 + lane;
+            item[u] = i < cnt ? queue[i].item : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kScan; ++u) {
+            const unsigned long long i = (ch + u * G) * 64 + lane;
+            const bool marked = (item[u] & kHardMark) != 0u;
+            const uint64_t mm = __ballot(marked);
+            if (marked) {
+                const int slot = n + __popcll(mm & below);
+                SI[slot] = (uint32_t)i;
+                ST[slot] = (uint16_t)((item[u] >> kHardTryShift) & 7u);
+            }
+            n += __popcll(mm);
+        }
+        ch += kScan * G;
     }
 }
 
