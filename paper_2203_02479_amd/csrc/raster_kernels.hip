@@ -581,6 +581,29 @@ __device__ __forceinline__ bool rejection_regime(int mode, float q, double p) {
 // keeps the steps of the lanes of one batch close together.
 enum { kStkZ = 0, kStkI = 1, kStkJ = 2, kStkF = 3, kStacks = 4 };
 
+// The same classification from the float product pf (p = (double)pf) in
+// float arithmetic: only the rejection boundary (mean 10) must agree with
+// the samplers' own FP64 test, and a float mean more than 1e-4 away from 10
+// is on the same side of it (float rounding here is below 1e-6 relative);
+// the few bins closer to it take the FP64 test.  The other boundaries only
+// pick a stack.
+__device__ __forceinline__ int sampler_stack(int mode, float q, double p);
+
+__device__ __forceinline__ int sampler_stack_f(int mode, float q, float pf) {
+    const float aq = fabsf(q);
+    float mean;
+    if (mode == 1) {
+        const float n = rintf(aq);
+        if (!(n > 0.f) || !(pf > 0.f) || pf >= 1.f) return kStkZ;
+        mean = n * (pf > 0.5f ? 1.f - pf : pf);
+    } else {
+        mean = aq * pf;
+        if (!(mean > 0.f)) return kStkZ;
+    }
+    if (mean > 9.999f && mean < 10.001f) return sampler_stack(mode, q, (double)pf);
+    return mean >= 10.f ? kStkF : mean < 1.f ? kStkZ : mean < 4.f ? kStkI : kStkJ;
+}
+
 __device__ __forceinline__ int sampler_stack(int mode, float q, double p) {
 #pragma clang fp contract(off)
     double aq = fabs((double)q);
@@ -806,15 +829,20 @@ __device__ __forceinline__ bool depo_finite(float a, float b, float c, float d, 
     return isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) && isfinite(e);
 }
 
-__device__ __forceinline__ int wave_min(int v) {
+// Min / max over the first kSub lanes (the only ones holding values), as a
+// scalar loop over lane reads: no LDS round trips (a shuffle reduction is a
+// chain of ds_bpermute).
+__device__ __forceinline__ int sub_min(int v) {
+    int r = __builtin_amdgcn_readlane(v, 0);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+    for (int l = 1; l < kSub; ++l) r = min(r, __builtin_amdgcn_readlane(v, l));
+    return r;
 }
-__device__ __forceinline__ int wave_max(int v) {
+__device__ __forceinline__ int sub_max(int v) {
+    int r = __builtin_amdgcn_readlane(v, 0);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    for (int l = 1; l < kSub; ++l) r = max(r, __builtin_amdgcn_readlane(v, l));
+    return r;
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -893,22 +921,20 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             jlo_[lane] = jlo; nt_[lane] = nt; mlo_[lane] = mlo; nx_[lane] = nx; q_[lane] = q;
         }
         // wave-uniform bounds, held in scalar registers
-        const int jmin = __builtin_amdgcn_readfirstlane(wave_min(bj0));
-        const int jmax = __builtin_amdgcn_readfirstlane(wave_max(bj1));
-        const int mmin = __builtin_amdgcn_readfirstlane(wave_min(bm0));
-        const int mmax = __builtin_amdgcn_readfirstlane(wave_max(bm1));
+        const int jmin = sub_min(bj0), jmax = sub_max(bj1);
+        const int mmin = sub_min(bm0), mmax = sub_max(bm1);
         if (jmax < jmin) continue;   // no regular depo in this sub-chunk (uniform)
         const int span_t = jmax - jmin + 1, span_x = mmax - mmin + 1;
         const bool use_tile = span_t * span_x <= kWaveTile;
-        if (FLUCT) {   // exclusive prefix of cell counts over the sub-chunk
-            int v = cells;
+        if (FLUCT) {   // exclusive prefix of cell counts over the sub-chunk (scalar)
+            int acc = 0, mine = 0;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                int u = __shfl_up(v, o, 64);
-                if (lane >= o) v += u;
+            for (int l = 0; l < kSub; ++l) {
+                if (lane == l) mine = acc;
+                acc += __builtin_amdgcn_readlane(cells, l);
             }
-            if (lane < kSub) s_off[wv][lane] = v - cells;
-            if (lane == kSub - 1) s_off[wv][kSub] = v;
+            if (lane < kSub) s_off[wv][lane] = mine;
+            if (lane == kSub) s_off[wv][kSub] = acc;
         }
         // ---- weights: lanes 0..kSub-1 time axis, kSub..2kSub-1 pitch axis
         {
@@ -999,7 +1025,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                         const int j = jlo_[dd] + b;
                         const int m = mlo_[dd] + a;
                         const double p = (double)(w[b] * w[kMaxT + a]);
-                        const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                        const uint32_t bin = (uint32_t)m * (uint32_t)A.n_ticks + (uint32_t)j;
                         const uint32_t dg = (uint32_t)(base + dd);
                         if (st == kStkZ)
                             v = bin_count_fast<MODE, kStageZero>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
@@ -1083,9 +1109,8 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
                     const int b = local - a * ant;
                     const float* w = W + d * kSlot;
-                    const double p = (double)(w[b] * w[kMaxT + a]);
                     code = (d << 9) | (a << 4) | b;
-                    sk = sampler_stack(MODE, q_[d], p);
+                    sk = sampler_stack_f(MODE, q_[d], w[b] * w[kMaxT + a]);
                 }
                 const uint64_t below = (1ull << lane) - 1;
 #pragma unroll
