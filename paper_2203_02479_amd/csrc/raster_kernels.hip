@@ -767,19 +767,20 @@ __device__ __forceinline__ float single_weight(double mu, double sg, double org,
 // Every wave works alone on sub-chunks of kSub consecutive depos: windows,
 // weights into its LDS slots, patches summed into its private LDS tile over
 // the sub-chunk's bounding box, then one global float atomic per non-zero
-// tile cell.  A wave instruction never has two lanes on the same tile cell
-// (the mean path covers one depo per instruction; the fluctuated path adds
-// the lanes of one depo at a time), so the tile is accumulated with plain
-// LDS read-add-write: float atomics in LDS are slower than in L2 on this
-// chip.  Sub-chunks whose box exceeds the tile go straight to global atomics.
+// tile cell.  The mean path covers one depo per instruction, so no two
+// lanes of an instruction share a tile cell and the tile takes plain LDS
+// read-add-write; the fluctuated path draws batches that mix depos and adds
+// with LDS float atomics.  Sub-chunks whose box exceeds the tile go straight
+// to global atomics.
 //
-// Fluctuation runs in three kernels so that the hot one stays small in
+// Fluctuation runs in several kernels so that the hot one stays small in
 // registers: k_raster draws every bin by inversion or in the rejection
 // samplers' fast region and queues the rest in the workspace;
-// k_raster_deferred redraws the queued bins with the full samplers;
-// k_raster_overflow redraws all deferred bins of sub-chunks whose queue
-// reservation did not fit.  A bin's count depends only on its counter, so
-// which kernel draws it does not change the result.
+// k_raster_deferred and k_raster_hard redraw the queued bins with the rest
+// of the samplers; k_raster_flagged takes the sub-chunks whose queue
+// reservation did not fit and the depos too wide for the weight slots.  A
+// bin's count depends only on its counter, so which kernel draws it does
+// not change the result.
 
 static constexpr int kRasterThreads = 256;
 static constexpr int kWaves = kRasterThreads / 64;
@@ -806,6 +807,9 @@ struct RasterWs {
 };
 static constexpr uint32_t kHardMark = 0x80000000u;   // DeferredBin::item bit: left to k_raster_hard
 static constexpr uint32_t kInvMark = 0x08000000u;    // ... an inversion bin (else a rejection one)
+// sub-chunk flag bits (one byte per sub-chunk, cleared by k_raster_reset)
+static constexpr int kFlagOverflow = 1;   // some of its deferred bins did not fit in the queue
+static constexpr int kFlagWide = 2;       // it holds a depo wider than the weight slots
 
 int64_t raster_subchunks(int64_t n) { return (n + kSub - 1) / kSub; }
 
@@ -868,7 +872,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
     __shared__ uint16_t s_list[kWaves][kStacks][FLUCT ? 128 : 1];    // cells by sampler stack
     __shared__ double s_rcp[FLUCT ? kRcpTable : 1];                  // 1/k, k < kRcpTable
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* W = s_w[wv];
     float* tile = s_tile[wv];
     int* jlo_ = s_meta[wv][0];
@@ -897,6 +901,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
         const int64_t base = (gsub - I.sub_begin) * kSub;
         // ---- windows: lane d < kSub takes depo base + d
         int nt = 0, nx = 0, jlo = 0, mlo = 0, cells = 0;
+        bool wide = false;
         int bj0 = INT_MAX, bj1 = INT_MIN, bm0 = INT_MAX, bm1 = INT_MIN;
         if (lane < kSub) {
             int64_t d = base + lane;
@@ -915,6 +920,8 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                         mlo = wx.lo;
                         cells = wt.n * wx.n;
                         bj0 = jlo; bj1 = jlo + wt.n - 1; bm0 = mlo; bm1 = mlo + wx.n - 1;
+                    } else {
+                        wide = wt.n && wx.n;
                     }
                 }
             }
@@ -923,7 +930,12 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
         // wave-uniform bounds, held in scalar registers
         const int jmin = sub_min(bj0), jmax = sub_max(bj1);
         const int mmin = sub_min(bm0), mmax = sub_max(bm1);
-        if (jmax < jmin) continue;   // no regular depo in this sub-chunk (uniform)
+        // wave-uniform flag byte of this sub-chunk, stored at its end
+        int fl = (FLUCT && __ballot(wide)) ? kFlagWide : 0;
+        if (jmax < jmin) {   // no regular depo in this sub-chunk (uniform)
+            if (fl && lane == 0) flags[gsub] = (uint8_t)fl;
+            continue;
+        }
         const int span_t = jmax - jmin + 1, span_x = mmax - mmin + 1;
         const bool use_tile = span_t * span_x <= kWaveTile;
         if (FLUCT) {   // exclusive prefix of cell counts over the sub-chunk (scalar)
@@ -1092,7 +1104,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                             }
                             queue[slot] = db;
                         }
-                        if (!fits && lane == 0) flags[gsub] = 1;
+                        if (!fits) fl |= kFlagOverflow;
                         nq = 0;
                         wave_lds_sync();
                     }
@@ -1134,6 +1146,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                 }
             }
         }
+        if (FLUCT && fl && lane == 0) flags[gsub] = (uint8_t)fl;
     }
 }
 
@@ -1144,7 +1157,7 @@ __global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
     for (; i < nsub; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
-// The queued bins (skipping those of sub-chunks left to k_raster_overflow),
+// The queued bins (skipping those of sub-chunks left to k_raster_flagged),
 // in two converged stages per wave: every bin first runs the whole first try
 // of the rejection sampler; the bins whose first try was rejected resume the
 // fast sampler at the second try (up to kFastTries), collected in a
@@ -1185,7 +1198,7 @@ void k_raster_deferred(
     RasterItem one, const RasterItem* __restrict__ items, RasterWs* __restrict__ ws,
     const uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue, unsigned long long cap) {
     __shared__ uint32_t s_stk[kDefWaves][128];   // queue indices of resumed bins
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* S1 = s_stk[wv];
     const unsigned long long cnt = min(ws->count, cap);
     const unsigned long long nchunk = (cnt + 63) / 64;
@@ -1213,7 +1226,8 @@ void k_raster_deferred(
         if (i < cnt) {
             const DeferredBin db = queue[i];
             const RasterItem& I = items ? items[db.item & (kInvMark - 1u)] : one;
-            if (db.depo != kInvalid && !(db.item & kHardMark) && !flags[I.sub_begin + db.depo / kSub]) {
+            if (db.depo != kInvalid && !(db.item & kHardMark) &&
+                !(flags[I.sub_begin + db.depo / kSub] & kFlagOverflow)) {
                 int next = 0;
                 const float v = deferred_draw<MODE, kStageSecond>(one, items, db, &next);
                 if (v != v) {
@@ -1237,17 +1251,20 @@ void k_raster_deferred(
 // is rejected goes back on the stack with the next try.  The scan reads
 // kScan chunks at a time so that their loads overlap.  (Running each bin
 // to its end in one pass kept a wave busy for the longest lane's several
-// tries.)  Inversion bins (queued by k_raster) take the full inversion.
+// tries.)  Inversion bins (queued by k_raster) take the full inversion;
+// those of a sub-chunk whose later bins overflowed the queue are skipped, as
+// k_raster_flagged redraws every deferred bin of such a sub-chunk.
 template <int MODE>
 __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
                                                                const RasterItem* __restrict__ items,
                                                                const RasterWs* __restrict__ ws,
+                                                               const uint8_t* __restrict__ flags,
                                                                const DeferredBin* __restrict__ queue,
                                                                unsigned long long cap) {
     constexpr int kScan = 4;                 // chunks of 64 entries scanned per step
     __shared__ uint32_t s_idx[kDefWaves][64 * (kScan + 2)];
     __shared__ uint16_t s_try[kDefWaves][64 * (kScan + 2)];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* SI = s_idx[wv];
     uint16_t* ST = s_try[wv];
     const unsigned long long cnt = min(ws->count, cap);
@@ -1271,13 +1288,15 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
                 db.item &= kInvMark - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
                 const RasterArgs& A = I.A;
-                const float q = I.q[db.depo];
-                const float v = inv ? bin_count_in<false>(MODE, q, (double)db.p, A.seed, db.depo, A.event,
-                                                          db.bin, A.plane)
-                                    : bin_count_in<true>(MODE, q, (double)db.p, A.seed, db.depo, A.event,
-                                                         db.bin, A.plane, t, t + 1);
-                if (v != v) again = true;
-                else if (v != 0.f) deferred_add(one, items, db, v);
+                if (!(flags[I.sub_begin + db.depo / kSub] & kFlagOverflow)) {
+                    const float q = I.q[db.depo];
+                    const float v = inv ? bin_count_in<false>(MODE, q, (double)db.p, A.seed, db.depo,
+                                                              A.event, db.bin, A.plane)
+                                        : bin_count_in<true>(MODE, q, (double)db.p, A.seed, db.depo,
+                                                             A.event, db.bin, A.plane, t, t + 1);
+                    if (v != v) again = true;
+                    else if (v != 0.f) deferred_add(one, items, db, v);
+                }
             }
             n -= c;
             const uint64_t mm = __ballot(again);
@@ -1315,56 +1334,82 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
     }
 }
 
-// Sub-chunks whose deferred bins did not fit in the queue: recompute their
-// regular depos' bins and draw the deferred ones (rejection-regime bins
-// that the first try's immediate acceptance did not decide, inversion bins
-// whose search ran off its end) with the full samplers.
+// Flagged sub-chunks of a fluctuated raster.  A workgroup reads the flag
+// bytes of 256 consecutive sub-chunks at once (one per thread) and takes the
+// flagged ones in turn, one cell per thread:
+//   kFlagWide      its depos wider than k_raster's weight slots: every bin,
+//                  with weights per cell and the one-shot sampler;
+//   kFlagOverflow  its regular depos' deferred bins (rejection-regime bins
+//                  that the first try's immediate acceptance did not decide,
+//                  inversion bins whose search ran off its end), recognised
+//                  by redrawing the fast stage, then drawn with the full
+//                  samplers; k_raster_deferred and k_raster_hard skip them.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_raster_overflow(RasterItem one, const RasterItem* __restrict__ items,
-                                                         int n_items, int64_t total_sub,
-                                                         const uint8_t* __restrict__ flags) {
-    for (int64_t gsub = blockIdx.x; gsub < total_sub; gsub += gridDim.x) {
-        if (!flags[gsub]) continue;
-        const RasterItem& I = items ? items[item_of(items, n_items, gsub)] : one;
-        const RasterArgs& A = I.A;
-        const int64_t sub = gsub - I.sub_begin;
-        for (int dd = 0; dd < kSub; ++dd) {
-            const int64_t gd = sub * kSub + dd;
-            if (gd >= I.n) break;
-            const float q = I.q[gd], t = I.t[gd], x = I.x[gd], st = I.st[gd], sx = I.sx[gd];
-            if (!depo_finite(q, t, x, st, sx)) continue;
-            const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
-            if (!wt.n) continue;
-            const Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
-            if (!wx.n || wt.n > kMaxT || wx.n > kMaxX) continue;
-            const int ncell = wt.n * wx.n;
-            for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-                const int a = c / wt.n, b = c - a * wt.n;
-                const float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
-                const float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
-                const int j = wt.lo + b, m = wx.lo + a;
-                const double p = (double)(wtv * wxv);
-                const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                // queued by k_raster: rejection bins the first stage left, and
-                // inversion bins (Z, I, J) whose one-try search ran off its end
-                const bool rej = sampler_stack(MODE, q, p) == kStkF;
-                float v = rej ? bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane)
-                              : bin_count_fast<MODE, kStageInv>(q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                if (v != v) {   // draw it here
-                    v = rej ? bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane)
-                            : bin_count_in<false>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+__global__ __launch_bounds__(256) void k_raster_flagged(RasterItem one, const RasterItem* __restrict__ items,
+                                                        int n_items, int64_t total_sub,
+                                                        const uint8_t* __restrict__ flags) {
+    __shared__ int s_list[256];
+    __shared__ int s_n;
+    for (int64_t g0 = (int64_t)blockIdx.x * 256; g0 < total_sub; g0 += (int64_t)gridDim.x * 256) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        const int64_t g = g0 + threadIdx.x;
+        if (g < total_sub && flags[g]) s_list[atomicAdd(&s_n, 1)] = (int)threadIdx.x;
+        __syncthreads();
+        const int nf = s_n;
+        for (int f = 0; f < nf; ++f) {
+            const int64_t gsub = g0 + s_list[f];
+            const int fl = flags[gsub];
+            const RasterItem& I = items ? items[item_of(items, n_items, gsub)] : one;
+            const RasterArgs& A = I.A;
+            const int64_t sub = gsub - I.sub_begin;
+            for (int dd = 0; dd < kSub; ++dd) {
+                const int64_t gd = sub * kSub + dd;
+                if (gd >= I.n) break;
+                const float q = I.q[gd], t = I.t[gd], x = I.x[gd], st = I.st[gd], sx = I.sx[gd];
+                if (!depo_finite(q, t, x, st, sx)) continue;
+                const Window wt = axis_window(t, st, A.nsig, A.org_t, A.wd_t, A.n_ticks);
+                if (!wt.n) continue;
+                const Window wx = axis_window(x, sx, A.nsig, A.org_x, A.wd_x, A.n_rows);
+                if (!wx.n) continue;
+                const bool wide = wt.n > kMaxT || wx.n > kMaxX;
+                if (!(fl & (wide ? kFlagWide : kFlagOverflow))) continue;
+                const int64_t ncell = (int64_t)wt.n * wx.n;
+                for (int64_t c = threadIdx.x; c < ncell; c += blockDim.x) {
+                    const int a = (int)(c / wt.n), b = (int)(c - (int64_t)a * wt.n);
+                    const float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
+                    const float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
+                    const int j = wt.lo + b, m = wx.lo + a;
+                    const double p = (double)(wtv * wxv);
+                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
+                    float v;
+                    if (wide) {
+                        v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                    } else {
+                        // the bins k_raster queued: rejection bins the first stage
+                        // left, inversion bins whose one-try search ran off its end
+                        const bool rej = sampler_stack(MODE, q, p) == kStkF;
+                        v = rej ? bin_count_fast<MODE, kStageFirst>(q, p, A.seed, (uint32_t)gd, A.event, bin,
+                                                                    A.plane)
+                                : bin_count_fast<MODE, kStageInv>(q, p, A.seed, (uint32_t)gd, A.event, bin,
+                                                                  A.plane);
+                        if (v == v) continue;   // drawn (and added) by k_raster
+                        v = rej ? bin_count_in<true>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane)
+                                : bin_count_in<false>(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                    }
                     if (v != 0.f) grid_add(&I.grid[(int64_t)m * A.ld + j], v);
                 }
             }
         }
+        __syncthreads();
     }
 }
 
-// Depos whose window exceeds the weight slots of k_raster (kMaxT ticks or
-// kMaxX impact rows): a workgroup scans kRasterThreads / kSub sub-chunks,
+// Mean raster: depos whose window exceeds the weight slots of k_raster (kMaxT
+// ticks or kMaxX impact rows): a workgroup scans kRasterThreads / kSub sub-chunks,
 // one depo slot per thread, and processes the wide depos cooperatively, one
-// cell per thread with weights per cell.
-template <int MODE>
+// cell per thread with weights per cell.  (Fluctuated rasters flag such
+// sub-chunks in k_raster and take them in k_raster_flagged.)
 __global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterItem one,
                                                                 const RasterItem* __restrict__ items,
                                                                 int n_items, int64_t total_sub) {
@@ -1407,14 +1452,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterItem one,
                 const float wtv = single_weight(t, st, A.org_t, A.wd_t, wt, b);
                 const float wxv = single_weight(x, sx, A.org_x, A.wd_x, wx, a);
                 const int j = wt.lo + b, m = wx.lo + a;
-                float v;
-                if (MODE == 0) {
-                    v = q * wtv * wxv;
-                } else {
-                    const double p = (double)(wtv * wxv);
-                    const uint32_t bin = (uint32_t)((int64_t)m * A.n_ticks + j);
-                    v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
-                }
+                const float v = q * wtv * wxv;
                 if (v != 0.f) grid_add(&I.grid[(int64_t)m * A.ld + j], v);
             }
         }
@@ -1535,7 +1573,7 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
         hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, one, items, n_items, total_sub, nullptr, nullptr,
                            nullptr, 0ull);
         if (main_done) (void)hipEventRecord(main_done, s);
-        hipLaunchKernelGGL(k_raster_wide<0>, gw, blk, 0, s, one, items, n_items, total_sub);
+        hipLaunchKernelGGL(k_raster_wide, gw, blk, 0, s, one, items, n_items, total_sub);
         return hipGetLastError();
     }
     const size_t fixed = raster_ws_fixed_subs(total_sub);
@@ -1546,9 +1584,8 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     const unsigned long long cap =
         std::min<unsigned long long>((ws_bytes - fixed) / sizeof(DeferredBin), 0xFFFFFFFFull);
     const int64_t rblk = (total_sub + 255) / 256;
-    hipLaunchKernelGGL(k_raster_reset, dim3((unsigned)(rblk < cap_blocks ? rblk : cap_blocks)), dim3(256),
-                       0, s, hdr, flags, total_sub);
-    dim3 gsub((unsigned)(total_sub < cap_blocks ? total_sub : cap_blocks));
+    const dim3 g256((unsigned)(rblk < cap_blocks ? rblk : cap_blocks));   // 256 sub-chunks per block
+    hipLaunchKernelGGL(k_raster_reset, g256, dim3(256), 0, s, hdr, flags, total_sub);
 #define LAR_FLUCT(M)                                                                                 \
     hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
                        cap);                                                                         \
@@ -1556,10 +1593,8 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s,  \
                        one, items, hdr, flags, queue, cap);                                          \
     hipLaunchKernelGGL(k_raster_hard<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s, one,  \
-                       items, hdr, queue, cap);                                                      \
-    hipLaunchKernelGGL(k_raster_overflow<M>, gsub, dim3(256), 0, s, one, items, n_items, total_sub,   \
-                       flags);                                                                       \
-    hipLaunchKernelGGL(k_raster_wide<M>, gw, blk, 0, s, one, items, n_items, total_sub);
+                       items, hdr, flags, queue, cap);                                               \
+    hipLaunchKernelGGL(k_raster_flagged<M>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     if (mode == 1) {
         LAR_FLUCT(1)
     } else {

@@ -278,6 +278,29 @@ def test_fluct_queue_capacity_does_not_change_counts(mode):
         gpu_raster(P, dep, fluct=fl, ws_bytes=fixed - 256)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_fluct_wide_depos_with_queue_overflow(mode):
+    """Depos wider than the hot raster kernel's weight slots (16 ticks, 32
+    impact rows), mixed with regular ones in the same sub-chunks: the oracle's
+    counts on nearly every bin, and the same counts with a queue of a few
+    entries or none (the flagged sub-chunks are then drawn by one kernel for
+    both reasons)."""
+    P = inputs.Plane(n_wires=24, n_ticks=400, n_imp=10)
+    dep = inputs.random_depos(P, 240, seed=12)
+    dep.sigma_t[::3] *= 4.0
+    dep.sigma_x[1::3] *= 3.0
+    fl = (mode, 77, 0, 1)
+    full = gpu_raster(P, dep, fluct=fl)
+    ref = oracle.raster_fluct(P, dep, mode=mode, seed=77, event=0, plane_id=1)
+    assert np.array_equal(full, np.round(full))
+    nz = (full != 0) | (ref != 0)
+    assert np.mean(full[nz] == ref[nz]) > 0.999
+    n = len(dep)
+    fixed = 256 + ((n + 15) // 16 + 255) // 256 * 256
+    for nb in (fixed, fixed + 16 * 37):
+        assert np.array_equal(gpu_raster(P, dep, fluct=fl, ws_bytes=nb), full)
+
+
 def test_fluct_point_charges_large_q():
     """Point-like and high-charge depos: every bin in the rejection regime."""
     P = inputs.Plane(n_wires=16, n_ticks=200, n_imp=10)
