@@ -790,6 +790,12 @@ static constexpr int kMaxX = 32;
 static constexpr int kSlot = kMaxT + kMaxX + 1;
 static constexpr int kWaveTile = 512;     // floats of a wave's private tile
 static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
+// k_raster's grid is capped at this many workgroups per CU; below the cap
+// every wave takes one sub-chunk and the workgroup dispatcher balances the
+// uneven sub-chunks (a persistent grid of 8 per CU, about 4 sub-chunks per
+// wave, was 13% slower on track depos)
+static constexpr int kRasterGroupsPerCU = 64;
+static constexpr int kDeferredGroupsPerCU = 8;
 static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
 // Deferred bin: item, depo index within the item, bin index m * n_ticks + j
@@ -1201,6 +1207,7 @@ void k_raster_deferred(
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* S1 = s_stk[wv];
     const unsigned long long cnt = min(ws->count, cap);
+    const bool overflowed = ws->count > cap;   // else no sub-chunk is flagged for it
     const unsigned long long nchunk = (cnt + 63) / 64;
     int n1 = 0;   // wave-uniform
     const uint64_t below = (1ull << lane) - 1;
@@ -1227,7 +1234,7 @@ void k_raster_deferred(
             const DeferredBin db = queue[i];
             const RasterItem& I = items ? items[db.item & (kInvMark - 1u)] : one;
             if (db.depo != kInvalid && !(db.item & kHardMark) &&
-                !(flags[I.sub_begin + db.depo / kSub] & kFlagOverflow)) {
+                !(overflowed && (flags[I.sub_begin + db.depo / kSub] & kFlagOverflow))) {
                 int next = 0;
                 const float v = deferred_draw<MODE, kStageSecond>(one, items, db, &next);
                 if (v != v) {
@@ -1268,6 +1275,7 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
     uint32_t* SI = s_idx[wv];
     uint16_t* ST = s_try[wv];
     const unsigned long long cnt = min(ws->count, cap);
+    const bool overflowed = ws->count > cap;   // else no sub-chunk is flagged for it
     const unsigned long long nchunk = (cnt + 63) / 64;
     const uint64_t below = (1ull << lane) - 1;
     int n = 0;   // wave-uniform
@@ -1288,7 +1296,7 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
                 db.item &= kInvMark - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
                 const RasterArgs& A = I.A;
-                if (!(flags[I.sub_begin + db.depo / kSub] & kFlagOverflow)) {
+                if (!(overflowed && (flags[I.sub_begin + db.depo / kSub] & kFlagOverflow))) {
                     const float q = I.q[db.depo];
                     const float v = inv ? bin_count_in<false>(MODE, q, (double)db.p, A.seed, db.depo,
                                                               A.event, db.bin, A.plane)
@@ -1565,8 +1573,10 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
                                hipEvent_t main_done) {
     if (total_sub <= 0) return hipSuccess;
     const int64_t cap_blocks = 8 * (int64_t)device_cus();
+    const int64_t dgrid = kDeferredGroupsPerCU * (int64_t)device_cus();
     const int64_t nblk = (total_sub + kWaves - 1) / kWaves;
-    dim3 grd((unsigned)(nblk < cap_blocks ? nblk : cap_blocks)), blk(kRasterThreads);
+    const int64_t rcap = kRasterGroupsPerCU * (int64_t)device_cus();
+    const dim3 grd((unsigned)(nblk < rcap ? nblk : rcap)), blk(kRasterThreads);
     const int64_t nwide = (total_sub + (kRasterThreads / kSub) - 1) / (kRasterThreads / kSub);
     dim3 gw((unsigned)(nwide < cap_blocks ? nwide : cap_blocks));
     if (mode == 0) {
@@ -1590,9 +1600,9 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
                        cap);                                                                         \
     if (main_done) (void)hipEventRecord(main_done, s);                                               \
-    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s,  \
+    hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)dgrid), dim3(kDefWaves * 64), 0, s,       \
                        one, items, hdr, flags, queue, cap);                                          \
-    hipLaunchKernelGGL(k_raster_hard<M>, dim3((unsigned)cap_blocks), dim3(kDefWaves * 64), 0, s, one,  \
+    hipLaunchKernelGGL(k_raster_hard<M>, dim3((unsigned)dgrid), dim3(kDefWaves * 64), 0, s, one,       \
                        items, hdr, flags, queue, cap);                                               \
     hipLaunchKernelGGL(k_raster_flagged<M>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     if (mode == 1) {
