@@ -145,6 +145,18 @@ __device__ __forceinline__ double ipow_n(double x, double n) {
     const uint32_t hi0 = __builtin_amdgcn_readfirstlane((uint32_t)(e >> 32));
     const uint64_t e0 = ((uint64_t)hi0 << 32) | lo0;
     if (__ballot(e != e0) == 0) {
+        if (hi0 == 0u) {   // 32-bit exponent: the loop ends at its last bit
+            uint32_t es = lo0;
+            if (es) {
+                for (;;) {
+                    if (es & 1u) r = r * b;
+                    es >>= 1;
+                    if (!es) break;
+                    b = b * b;
+                }
+            }
+            return r;
+        }
         for (uint64_t es = e0; es; ) {
             if (es & 1u) r = r * b;
             es >>= 1;
@@ -190,24 +202,28 @@ __device__ __forceinline__ double binom_inversion(double n, double p, PhiloxStre
         if (rtab) {
             // 1/k correctly rounded, from the table (kRcpTable entries); the
             // next step's entry is loaded one step ahead
+            // one exit test per step (two exits cost the wave a set of
+            // exec-mask updates per step)
             double ik_next = rtab[1];
-            for (;;) {
-                if (u < f) return (double)k;
-                if (k >= kmax) break;
+            bool hit = u < f;
+            while (!hit && k < kmax) {
                 u = u - f;
                 ++k;
                 const double ik = ik_next;
                 ik_next = rtab[k + 1];
                 f = f * (g * ik - ratio);
+                hit = u < f;
             }
+            if (hit) return (double)k;
         } else {
-            for (;;) {
-                if (u < f) return (double)k;
-                if (k >= kmax) break;
+            bool hit = u < f;
+            while (!hit && k < kmax) {
                 u = u - f;
                 ++k;
                 f = f * (g * (1.0 / (double)k) - ratio);
+                hit = u < f;
             }
+            if (hit) return (double)k;
         }
     }
     return ONE_TRY ? -1.0 : floor(n * p);
