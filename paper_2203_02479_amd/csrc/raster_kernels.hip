@@ -330,8 +330,7 @@ __device__ double poisson_inversion(double lam, PhiloxStream& s) {
     for (int tries = 0; tries < (ONE_TRY ? 1 : LAR_MAX_TRIES); ++tries) {
         if (tries > 0) u = next_uniform(s);
         double p = p0, cdf = p0, k = 0.0;
-        while (u > cdf) {
-            if (k > 200.0) break;
+        while (u > cdf && !(k > 200.0)) {   // one exit test per step
             k = k + 1.0;
             p = p * lam / k;
             cdf = cdf + p;
@@ -594,8 +593,9 @@ __device__ __forceinline__ bool rejection_regime(int mode, float q, double p) {
 //   kStkI  mean in [1, 4): kStageInv       kStkJ  mean in [4, 10): kStageInv
 //   kStkF  the rejection regime (mean >= 10): kStageFirst
 // Inversion takes about mean + 1 steps; splitting its bins at a mean of 4
-// keeps the steps of the lanes of one batch close together.
-enum { kStkZ = 0, kStkI = 1, kStkJ = 2, kStkF = 3, kStacks = 4 };
+// keeps the steps of the lanes of one batch close together.  The numbering
+// is k_raster's drawing priority (I, J, Z, F).
+enum { kStkI = 0, kStkJ = 1, kStkZ = 2, kStkF = 3, kStacks = 4 };
 
 // The same classification from the float product pf (p = (double)pf) in
 // float arithmetic: only the rejection boundary (mean 10) must agree with
@@ -1034,26 +1034,27 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             // it, so every push of up to 64 codes fits.
             const int total = __builtin_amdgcn_readfirstlane(s_off[wv][kSub]);
             uint16_t* const L0 = s_list[wv][0];   // stack k at L0 + 128 k
-            int nL[kStacks] = {0, 0, 0, 0};   // wave-uniform stack sizes
+            // wave-uniform stack sizes (each below 128), byte k = stack k, so
+            // that the first stack holding thr or more codes is the lowest
+            // set bit of a mask
+            uint32_t nL = 0u;
             int nq = 0;                 // wave-uniform queue size
             int d = 0;
             int c0 = 0;
             for (;;) {
                 const bool tail = c0 >= total;
-                const int thr = tail ? 1 : 64;
-                const int st = nL[kStkI] >= thr   ? kStkI
-                               : nL[kStkJ] >= thr ? kStkJ
-                               : nL[kStkZ] >= thr ? kStkZ
-                               : nL[kStkF] >= thr ? kStkF
-                                                  : -1;
-                if (st >= 0) {   // one batch of 64 (or the rest) from stack st (wave-uniform)
+                // bytes >= 64: bit 6; bytes >= 1: bit 7 of byte + 127
+                const uint32_t ready = tail ? ((nL + 0x7f7f7f7fu) & 0x80808080u) : (nL & 0x40404040u);
+                if (ready) {   // one batch of 64 (or the rest) from stack st (wave-uniform)
+                    const int st = __builtin_ctz(ready) >> 3;
+                    const int nst = (int)((nL >> (8 * st)) & 0xffu);
                     wave_lds_sync();
-                    const int cnt = min(nL[st], 64);
+                    const int cnt = min(nst, 64);
                     int todo = -1, code = 0;
                     bool defer = false, move = false;
                     float v = 0.f;
                     if (lane < cnt) {
-                        code = L0[st * 128 + nL[st] - cnt + lane];
+                        code = L0[st * 128 + nst - cnt + lane];
                         const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
                         const float* w = W + dd * kSlot;
                         const int j = jlo_[dd] + b;
@@ -1075,12 +1076,13 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                             todo = dd;
                         }
                     }
-                    nL[st] -= cnt;
+                    nL -= (uint32_t)cnt << (8 * st);
                     const uint64_t below = (1ull << lane) - 1;
                     if (st == kStkZ) {   // failed zero tests go to the low-mean inversion stack
                         const uint64_t mm = __ballot(move);
-                        if (move) L0[kStkI * 128 + nL[kStkI] + __popcll(mm & below)] = (uint16_t)code;
-                        nL[kStkI] += __popcll(mm);
+                        const int nI = (int)((nL >> (8 * kStkI)) & 0xffu);
+                        if (move) L0[kStkI * 128 + nI + __popcll(mm & below)] = (uint16_t)code;
+                        nL += (uint32_t)__popcll(mm) << (8 * kStkI);
                     }
                     if (st != kStkZ) {
                         const uint64_t dm = __ballot(defer);
@@ -1101,7 +1103,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     }
                     // move queued bins to the workspace when the next batch could
                     // overflow the buffer, and at the end of the sub-chunk
-                    const bool last = c0 >= total && nL[0] == 0 && nL[1] == 0 && nL[2] == 0 && nL[3] == 0;
+                    const bool last = c0 >= total && nL == 0u;
                     if (nq > kWaveQueue - 64 || (last && nq > 0)) {
                         wave_lds_sync();
                         unsigned long long gb = 0;
@@ -1150,8 +1152,8 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
 #pragma unroll
                 for (int k = 0; k < kStacks; ++k) {
                     const uint64_t mk = __ballot(sk == k);
-                    if (sk == k) L0[k * 128 + nL[k] + __popcll(mk & below)] = (uint16_t)code;
-                    nL[k] += __popcll(mk);
+                    if (sk == k) L0[k * 128 + (int)((nL >> (8 * k)) & 0xffu) + __popcll(mk & below)] = (uint16_t)code;
+                    nL += (uint32_t)__popcll(mk) << (8 * k);
                 }
                 c0 += 64;
             }
