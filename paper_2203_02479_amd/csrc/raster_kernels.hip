@@ -498,7 +498,10 @@ __device__ __forceinline__ int next_try(double code, int tries_of_stage) {
     return code == kTriesUsed ? kNextFast + tries_of_stage : (int)(-1.0 - code);
 }
 
-template <int MODE, int STAGE>
+// VALID: the caller guarantees n > 0 (lam > 0) and 0 < p < 1 (the bins of
+// k_raster's inversion and rejection stacks), so the trivial cases are not
+// tested.
+template <int MODE, int STAGE, bool VALID = false>
 __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed, uint32_t depo,
                                                 uint32_t event, uint32_t bin, uint32_t plane,
                                                 const double* rtab = nullptr, int* next = nullptr) {
@@ -514,9 +517,9 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
     double r;
     if (MODE == 1) {
         double n = rint(aq);
-        if (!(n > 0.0) || !(p > 0.0)) {
+        if (!VALID && (!(n > 0.0) || !(p > 0.0))) {
             r = 0.0;
-        } else if (p >= 1.0) {
+        } else if (!VALID && p >= 1.0) {
             r = n;
         } else {
             bool flip = p > 0.5;
@@ -544,7 +547,7 @@ __device__ __forceinline__ float bin_count_fast(float q, double p, uint64_t seed
         }
     } else {
         double lam = aq * p;
-        if (!(lam > 0.0)) {
+        if (!VALID && !(lam > 0.0)) {
             r = 0.0;
         } else {
             if (STAGE == kStageResume)
@@ -1034,6 +1037,11 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             // it, so every push of up to 64 codes fits.
             const int total = __builtin_amdgcn_readfirstlane(s_off[wv][kSub]);
             uint16_t* const L0 = s_list[wv][0];   // stack k at L0 + 128 k
+            // the item's constants, read once (not per batch through the
+            // item-or-table reference)
+            const uint64_t seed = A.seed;
+            const uint32_t event = A.event, plane = A.plane, nticks = (uint32_t)A.n_ticks;
+            const int64_t ld = A.ld;
             // wave-uniform stack sizes (each below 128), byte k = stack k, so
             // that the first stack holding thr or more codes is the lowest
             // set bit of a mask
@@ -1050,30 +1058,30 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     const int nst = (int)((nL >> (8 * st)) & 0xffu);
                     wave_lds_sync();
                     const int cnt = min(nst, 64);
-                    int todo = -1, code = 0;
-                    bool defer = false, move = false;
+                    int code = 0, m = 0, j = 0;
+                    bool todo = false, defer = false, move = false;
                     float v = 0.f;
                     if (lane < cnt) {
                         code = L0[st * 128 + nst - cnt + lane];
                         const int dd = code >> 9, a = (code >> 4) & 31, b = code & 15;
                         const float* w = W + dd * kSlot;
-                        const int j = jlo_[dd] + b;
-                        const int m = mlo_[dd] + a;
+                        j = jlo_[dd] + b;
+                        m = mlo_[dd] + a;
                         const double p = (double)(w[b] * w[kMaxT + a]);
-                        const uint32_t bin = (uint32_t)m * (uint32_t)A.n_ticks + (uint32_t)j;
+                        const uint32_t bin = (uint32_t)m * nticks + (uint32_t)j;
                         const uint32_t dg = (uint32_t)(base + dd);
                         if (st == kStkZ)
-                            v = bin_count_fast<MODE, kStageZero>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                            v = bin_count_fast<MODE, kStageZero>(q_[dd], p, seed, dg, event, bin, plane);
                         else if (st == kStkF)
-                            v = bin_count_fast<MODE, kStageFirst>(q_[dd], p, A.seed, dg, A.event, bin, A.plane);
+                            v = bin_count_fast<MODE, kStageFirst, true>(q_[dd], p, seed, dg, event, bin, plane);
                         else
-                            v = bin_count_fast<MODE, kStageInv>(q_[dd], p, A.seed, dg, A.event, bin, A.plane,
+                            v = bin_count_fast<MODE, kStageInv, true>(q_[dd], p, seed, dg, event, bin, plane,
                                                                 s_rcp);
                         if (v != v) {   // Z: to I; I, J (search ran off its end) and F: queued
                             if (st == kStkZ) move = true;
                             else defer = true;
                         } else if (v != 0.f) {
-                            todo = dd;
+                            todo = true;
                         }
                     }
                     nL -= (uint32_t)cnt << (8 * st);
@@ -1094,12 +1102,11 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     // add the drawn counts: two depos of one batch may share a cell,
                     // so the tile takes LDS atomics here (cheaper than serialising
                     // the lanes by depo, measured)
-                    if (todo >= 0) {   // the cell, recomputed from the code
-                        const int m = mlo_[todo] + ((code >> 4) & 31), j = jlo_[todo] + (code & 15);
+                    if (todo) {
                         if (use_tile)
                             atomicAdd(&tile[(m - mmin) * span_t + (j - jmin)], v);
                         else
-                            grid_add(&grid[(int64_t)m * A.ld + j], v);
+                            grid_add(&grid[(int64_t)m * ld + j], v);
                     }
                     // move queued bins to the workspace when the next batch could
                     // overflow the buffer, and at the end of the sub-chunk
@@ -1121,7 +1128,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                                 if (cd & 8192) db.item |= kHardMark | kInvMark;
                                 const float* w = W + dq * kSlot;
                                 db.depo = (uint32_t)(base + dq);
-                                db.bin = (uint32_t)((int64_t)(mlo_[dq] + a) * A.n_ticks + (jlo_[dq] + b));
+                                db.bin = (uint32_t)(mlo_[dq] + a) * nticks + (uint32_t)(jlo_[dq] + b);
                                 db.p = w[b] * w[kMaxT + a];
                             } else {
                                 db.depo = kInvalid; db.bin = 0; db.p = 0.f;
