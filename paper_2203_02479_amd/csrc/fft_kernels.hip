@@ -64,8 +64,25 @@ int device_cus() {
 
 
 // Half-angle table h[k] = exp(-pi i k / Nh) = exp(-2 pi i k / Tf), k < Nh,
-// computed in double and rounded once.
+// computed in double and rounded once.  When 4 divides Nh, only the first
+// octant's angles (k <= Nh/4) are evaluated and the other three quarters
+// of the table are their reflections (cos and sin swapped or negated): a
+// quarter of the double-precision sincospi calls, which each workgroup
+// makes before its first row.  Every entry is written by one thread.
 __device__ __forceinline__ void fill_half_table(float2* h, int Nh, int tid, int T) {
+    if ((Nh & 3) == 0) {
+        const int Q = Nh >> 2, H = Nh >> 1;
+        for (int i = tid; i <= Q; i += T) {
+            double s, c;
+            sincospi((double)i / (double)Nh, &s, &c);
+            const float fc = (float)c, fs = (float)s;
+            h[i] = make_float2(fc, -fs);                           // angle t
+            if (i >= 1 && i < Q) h[H - i] = make_float2(fs, -fc);  // pi/2 - t
+            if (i < Q) h[H + i] = make_float2(-fs, -fc);           // pi/2 + t
+            if (i >= 1) h[Nh - i] = make_float2(-fc, -fs);         // pi - t
+        }
+        return;
+    }
     for (int i = tid; i < Nh; i += T) {
         double s, c;
         sincospi(-(double)i / (double)Nh, &s, &c);
