@@ -104,8 +104,8 @@ int lar_last_hip_error(void);
  * exactly below 2^24).
  * Workspace: none for the mean patch (ws may be NULL); a fluctuated raster
  * queues in it (16 bytes each) the rejection-regime bins that the first
- * try's immediate acceptance does not decide, and draws them in a second
- * kernel.  lar_raster_workspace gives the recommended size for n_depos
+ * try's immediate acceptance does not decide, and draws them in later
+ * kernels.  lar_raster_workspace gives the recommended size for n_depos
  * (room for 48 such bins per depo); any size of
  * at least the size it gives for n_depos = depos->n with a queue of zero
  * (the sum of a 256-byte header and one byte per 16 depos, rounded up to
