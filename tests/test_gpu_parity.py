@@ -264,7 +264,7 @@ def test_fluct_chi2_mean_and_variance():
 def test_fluct_queue_capacity_does_not_change_counts(mode):
     """Bins beyond the rejection samplers' fast region go through the
     workspace queue; with a queue of zero or a few entries they are redrawn
-    by the overflow kernel instead.  Counts are integers: bit-identical."""
+    by the flagged-sub-chunk kernel instead.  Counts are integers: bit-identical."""
     ev = inputs.cfg0_event()
     P, dep = ev.planes[0], ev.depos[0]
     fl = (mode, 99, 4, 1)
