@@ -8,7 +8,7 @@ from paper_2203_02479_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _setup(n_events=3, fluct_mode=1, sizes=None, seed=7):
+def _setup(n_events=3, fluct_mode=1, sizes=None, seed=7, widen=False):
     import torch
     from paper_2203_02479_amd import lar
     planes = [inputs.Plane(n_wires=40, n_ticks=700, kind="bipolar"),
@@ -20,6 +20,9 @@ def _setup(n_events=3, fluct_mode=1, sizes=None, seed=7):
         for pl, pt in ((0, 0), (1, 0), (2, 1)):
             n = int(rng.integers(0, 3000)) if sizes is None else sizes[(e * 3 + pl) % len(sizes)]
             d = inputs.random_depos(planes[pt], n, seed=seed * 100 + e * 3 + pl, margin=0.1)
+            if widen:   # windows beyond the raster kernel's 16 x 32 weight slots
+                d.sigma_t[::5] *= 4.0
+                d.sigma_x[2::5] *= 3.0
             items.append((pt, e, pl, off, n, woff))
             deps.append(d)
             off += n
@@ -78,4 +81,25 @@ def test_batch_with_empty_items_and_one_item():
     torch.cuda.synchronize()
     ref = _reference(torch, lar, planes, resps, items, deps, fl, total)
     assert np.array_equal(wave.cpu().numpy(), ref)
+    b.close()
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_batch_with_wide_depos(mode):
+    """Depos wider than the hot raster kernel's weight slots, taken by the
+    flagged-sub-chunk kernel (fluctuated) or the wide-depo kernel (mean)
+    through the batch's item table: the same waveforms as per-item runs."""
+    torch, lar, planes, resps, items, deps, cat, fl, total = _setup(n_events=2, fluct_mode=mode, widen=True)
+    D = lar.DeviceDepos.from_host(cat)
+    wave = torch.zeros(total, device="cuda")
+    ws = lar.workspace(lar.batch_workspace(planes, items, fl))
+    b = lar.Batch(planes, resps, D, 3.0, fl, items, wave, ws)
+    b.run()
+    torch.cuda.synchronize()
+    ref = _reference(torch, lar, planes, resps, items, deps, fl, total)
+    got = wave.cpu().numpy()
+    if mode:
+        assert np.array_equal(got, ref)
+    else:
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-5 * np.abs(ref).max())
     b.close()
