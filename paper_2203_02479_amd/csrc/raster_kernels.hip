@@ -814,7 +814,7 @@ static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
 // uneven sub-chunks (a persistent grid of 8 per CU, about 4 sub-chunks per
 // wave, was 13% slower on track depos)
 static constexpr int kRasterGroupsPerCU = 64;
-static constexpr int kDeferredGroupsPerCU = 8;
+static constexpr int kDeferredGroupsPerCU = 8;   // a multiple of the queue's parts
 static constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
 // Deferred bin: item, depo index within the item, bin index m * n_ticks + j
@@ -827,9 +827,24 @@ static_assert(sizeof(DeferredBin) == kDeferredBytes, "queue record size");
 
 // Workspace of a fluctuated raster: header, one flag byte per sub-chunk,
 // then the queue.  The queue capacity is whatever the workspace holds.
-struct RasterWs {
-    unsigned long long count;    // bins queued (may exceed the capacity)
+// The queue is split in kQueueParts equal parts, each with its own counter
+// (k_raster's workgroup b reserves in part b mod kQueueParts): the
+// reservations, one per wave, spread over several addresses instead of
+// serialising on one.
+static constexpr int kQueueParts = 8;
+struct QueueCounter {
+    unsigned long long v;        // bins queued in the part (may exceed its room)
+    unsigned long long pad[3];   // one counter per 32 bytes
 };
+struct RasterWs {
+    QueueCounter count[kQueueParts];
+};
+static_assert(sizeof(RasterWs) <= 256, "raster workspace header");
+static_assert(kDeferredGroupsPerCU % kQueueParts == 0, "queue kernels take one part per workgroup");
+
+// Workgroup b of k_raster_deferred and k_raster_hard works on part
+// b mod kQueueParts (their grids are multiples of kQueueParts): the entries
+// of one sub-chunk, and so its overflow flag, belong to one part.
 static constexpr uint32_t kHardMark = 0x80000000u;   // DeferredBin::item bit: left to k_raster_hard
 static constexpr uint32_t kInvMark = 0x08000000u;    // ... an inversion bin (else a rejection one)
 // sub-chunk flag bits (one byte per sub-chunk, cleared by k_raster_reset)
@@ -1113,13 +1128,15 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     const bool last = c0 >= total && nL == 0u;
                     if (nq > kWaveQueue - 64 || (last && nq > 0)) {
                         wave_lds_sync();
+                        const int part = (int)(blockIdx.x % kQueueParts);
+                        const unsigned long long capr = cap / kQueueParts;
                         unsigned long long gb = 0;
-                        if (lane == 0) gb = atomicAdd(&ws->count, (unsigned long long)nq);
+                        if (lane == 0) gb = atomicAdd(&ws->count[part].v, (unsigned long long)nq);
                         gb = __shfl(gb, 0, 64);
-                        const bool fits = gb + (unsigned long long)nq <= cap;
+                        const bool fits = gb + (unsigned long long)nq <= capr;
                         for (int e = lane; e < nq; e += 64) {
-                            const unsigned long long slot = gb + (unsigned long long)e;
-                            if (slot >= cap) continue;
+                            if (gb + (unsigned long long)e >= capr) continue;
+                            const unsigned long long slot = (unsigned long long)part * capr + gb + e;
                             DeferredBin db;
                             db.item = (uint32_t)it;
                             if (fits) {
@@ -1184,7 +1201,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
 // Clears the queue counter and the sub-chunk flags.
 __global__ void k_raster_reset(RasterWs* ws, uint8_t* flags, int64_t nsub) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) ws->count = 0ull;
+    if (i < kQueueParts) ws->count[i].v = 0ull;
     for (; i < nsub; i += (int64_t)gridDim.x * blockDim.x) flags[i] = 0;
 }
 
@@ -1231,23 +1248,26 @@ void k_raster_deferred(
     __shared__ uint32_t s_stk[kDefWaves][128];   // queue indices of resumed bins
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* S1 = s_stk[wv];
-    const unsigned long long cnt = min(ws->count, cap);
-    const bool overflowed = ws->count > cap;   // else no sub-chunk is flagged for it
+    const unsigned part = blockIdx.x % kQueueParts;
+    const unsigned long long capr = cap / kQueueParts, used = ws->count[part].v;
+    const unsigned long long cnt = min(used, capr);
+    DeferredBin* const pq = queue + part * capr;   // this workgroup's part
+    const bool overflowed = used > capr;   // else no sub-chunk of the part is flagged for it
     const unsigned long long nchunk = (cnt + 63) / 64;
     int n1 = 0;   // wave-uniform
     const uint64_t below = (1ull << lane) - 1;
-    for (unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;;
-         ch += (unsigned long long)gridDim.x * kDefWaves) {
+    for (unsigned long long ch = (unsigned long long)(blockIdx.x / kQueueParts) * kDefWaves + wv;;
+         ch += (unsigned long long)(gridDim.x / kQueueParts) * kDefWaves) {
         const bool tail = ch >= nchunk;
         while (n1 >= 64 || (tail && n1 > 0)) {   // resumed bins, 64 at a time
             wave_lds_sync();   // stack entries written by other lanes
             const int c = min(n1, 64);
             if (lane < c) {
                 const uint32_t idx = S1[n1 - c + lane];
-                const DeferredBin db = queue[idx];
+                const DeferredBin db = pq[idx];
                 int next = 0;
                 const float v = deferred_draw<MODE, kStageResume>(one, items, db, &next);
-                if (v != v) defer_hard(queue, idx, next >= kNextFast ? next - kNextFast : next);
+                if (v != v) defer_hard(pq, idx, next >= kNextFast ? next - kNextFast : next);
                 else if (v != 0.f) deferred_add(one, items, db, v);
             }
             n1 -= c;
@@ -1256,7 +1276,7 @@ void k_raster_deferred(
         const unsigned long long i = ch * 64 + lane;
         bool resume = false;
         if (i < cnt) {
-            const DeferredBin db = queue[i];
+            const DeferredBin db = pq[i];
             const RasterItem& I = items ? items[db.item & (kInvMark - 1u)] : one;
             if (db.depo != kInvalid && !(db.item & kHardMark) &&
                 !(overflowed && (flags[I.sub_begin + db.depo / kSub] & kFlagOverflow))) {
@@ -1264,7 +1284,7 @@ void k_raster_deferred(
                 const float v = deferred_draw<MODE, kStageSecond>(one, items, db, &next);
                 if (v != v) {
                     if (next >= kNextFast) resume = true;      // first try rejected
-                    else defer_hard(queue, (uint32_t)i, next);  // log-scale test
+                    else defer_hard(pq, (uint32_t)i, next);  // log-scale test
                 } else if (v != 0.f) {
                     deferred_add(one, items, db, v);
                 }
@@ -1299,12 +1319,15 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t* SI = s_idx[wv];
     uint16_t* ST = s_try[wv];
-    const unsigned long long cnt = min(ws->count, cap);
-    const bool overflowed = ws->count > cap;   // else no sub-chunk is flagged for it
+    const unsigned part = blockIdx.x % kQueueParts;
+    const unsigned long long capr = cap / kQueueParts, used = ws->count[part].v;
+    const unsigned long long cnt = min(used, capr);
+    const DeferredBin* const pq = queue + part * capr;   // this workgroup's part
+    const bool overflowed = used > capr;   // else no sub-chunk of the part is flagged for it
     const unsigned long long nchunk = (cnt + 63) / 64;
     const uint64_t below = (1ull << lane) - 1;
     int n = 0;   // wave-uniform
-    unsigned long long ch = (unsigned long long)blockIdx.x * kDefWaves + wv;
+    unsigned long long ch = (unsigned long long)(blockIdx.x / kQueueParts) * kDefWaves + wv;
     for (;;) {
         const bool tail = ch >= nchunk;
         if (n >= 64 || (tail && n > 0)) {
@@ -1316,7 +1339,7 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
             if (lane < c) {
                 idx = SI[n - c + lane];
                 t = ST[n - c + lane];
-                DeferredBin db = queue[idx];
+                DeferredBin db = pq[idx];
                 const bool inv = (db.item & kInvMark) != 0u;
                 db.item &= kInvMark - 1u;
                 const RasterItem& I = items ? items[db.item] : one;
@@ -1344,12 +1367,12 @@ __global__ __launch_bounds__(kDefWaves * 64) void k_raster_hard(RasterItem one,
         if (tail) break;
         // scan kScan chunks (their loads in flight together); n < 64 here,
         // so up to 64 * kScan more entries fit
-        const unsigned long long G = (unsigned long long)gridDim.x * kDefWaves;
+        const unsigned long long G = (unsigned long long)(gridDim.x / kQueueParts) * kDefWaves;
         uint32_t item[kScan];
 #pragma unroll
         for (int u = 0; u < kScan; ++u) {
             const unsigned long long i = (ch + u * G) * 64 + lane;
-            item[u] = i < cnt ? queue[i].item : 0u;
+            item[u] = i < cnt ? pq[i].item : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kScan; ++u) {
