@@ -895,6 +895,36 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// Writes a wave's nq buffered deferred bins (codes in sq) to its queue part
+// at reservation gb (room capr per part).  A reservation that does not fit
+// writes invalid records in the room it has and returns false: the
+// sub-chunk is then flagged for k_raster_flagged.
+__device__ __forceinline__ bool queue_write(DeferredBin* queue, int part, unsigned long long capr,
+                                            unsigned long long gb, int nq, const uint16_t* sq,
+                                            const float* W, const int* mlo_, const int* jlo_, uint32_t item,
+                                            int64_t base, uint32_t nticks, int lane) {
+    const bool fits = gb + (unsigned long long)nq <= capr;
+    for (int e = lane; e < nq; e += 64) {
+        if (gb + (unsigned long long)e >= capr) continue;
+        const unsigned long long slot = (unsigned long long)part * capr + gb + e;
+        DeferredBin db;
+        db.item = item;
+        if (fits) {
+            const int cd = sq[e];
+            const int dq = (cd >> 9) & 15, a = (cd >> 4) & 31, b = cd & 15;
+            if (cd & 8192) db.item |= kHardMark | kInvMark;
+            const float* w = W + dq * kSlot;
+            db.depo = (uint32_t)(base + dq);
+            db.bin = (uint32_t)(mlo_[dq] + a) * nticks + (uint32_t)(jlo_[dq] + b);
+            db.p = w[b] * w[kMaxT + a];
+        } else {
+            db.depo = kInvalid; db.bin = 0; db.p = 0.f;
+        }
+        queue[slot] = db;
+    }
+    return fits;
+}
+
 // 5 waves per SIMD: the sampler stages fit 96 VGPRs, and the LDS of a
 // workgroup (about 29 KB) lets 5 workgroups share a CU
 template <int MODE>
@@ -1007,6 +1037,9 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
         }
         wave_lds_sync();
 
+        int nq = 0;   // wave-uniform count of the wave's buffered deferred bins
+        const int part = (int)(blockIdx.x % kQueueParts);
+        const unsigned long long capr = cap / kQueueParts;
         if (!FLUCT) {
             // ---- mean patches: one depo per instruction, lanes = rows x TW ticks
             for (int d = 0; d < kSub; ++d) {
@@ -1061,7 +1094,6 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             // that the first stack holding thr or more codes is the lowest
             // set bit of a mask
             uint32_t nL = 0u;
-            int nq = 0;                 // wave-uniform queue size
             int d = 0;
             int c0 = 0;
             for (;;) {
@@ -1124,35 +1156,16 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                             grid_add(&grid[(int64_t)m * ld + j], v);
                     }
                     // move queued bins to the workspace when the next batch could
-                    // overflow the buffer, and at the end of the sub-chunk
-                    const bool last = c0 >= total && nL == 0u;
-                    if (nq > kWaveQueue - 64 || (last && nq > 0)) {
+                    // overflow the buffer (the rest after the sub-chunk's tile
+                    // flush, which hides the wait for the reservation)
+                    if (nq > kWaveQueue - 64) {
                         wave_lds_sync();
-                        const int part = (int)(blockIdx.x % kQueueParts);
-                        const unsigned long long capr = cap / kQueueParts;
                         unsigned long long gb = 0;
                         if (lane == 0) gb = atomicAdd(&ws->count[part].v, (unsigned long long)nq);
                         gb = __shfl(gb, 0, 64);
-                        const bool fits = gb + (unsigned long long)nq <= capr;
-                        for (int e = lane; e < nq; e += 64) {
-                            if (gb + (unsigned long long)e >= capr) continue;
-                            const unsigned long long slot = (unsigned long long)part * capr + gb + e;
-                            DeferredBin db;
-                            db.item = (uint32_t)it;
-                            if (fits) {
-                                const int cd = s_queue[wv][e];
-                                const int dq = (cd >> 9) & 15, a = (cd >> 4) & 31, b = cd & 15;
-                                if (cd & 8192) db.item |= kHardMark | kInvMark;
-                                const float* w = W + dq * kSlot;
-                                db.depo = (uint32_t)(base + dq);
-                                db.bin = (uint32_t)(mlo_[dq] + a) * nticks + (uint32_t)(jlo_[dq] + b);
-                                db.p = w[b] * w[kMaxT + a];
-                            } else {
-                                db.depo = kInvalid; db.bin = 0; db.p = 0.f;
-                            }
-                            queue[slot] = db;
-                        }
-                        if (!fits) fl |= kFlagOverflow;
+                        if (!queue_write(queue, part, capr, gb, nq, s_queue[wv], W, mlo_, jlo_, (uint32_t)it, base,
+                                         nticks, lane))
+                            fl |= kFlagOverflow;
                         nq = 0;
                         wave_lds_sync();
                     }
@@ -1182,6 +1195,13 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                 c0 += 64;
             }
         }
+        // the last queue reservation is requested before the tile flush and
+        // used after it
+        unsigned long long gb = 0;
+        if (FLUCT && nq > 0) {
+            wave_lds_sync();
+            if (lane == 0) gb = atomicAdd(&ws->count[part].v, (unsigned long long)nq);
+        }
         // ---- flush: one global atomic per non-zero cell, leave the tile zeroed
         if (use_tile) {
             const int area = span_t * span_x;
@@ -1193,6 +1213,13 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                     tile[e] = 0.f;
                 }
             }
+        }
+        if (FLUCT && nq > 0) {
+            gb = __shfl(gb, 0, 64);
+            if (!queue_write(queue, part, capr, gb, nq, s_queue[wv], W, mlo_, jlo_, (uint32_t)it, base,
+                             (uint32_t)A.n_ticks, lane))
+                fl |= kFlagOverflow;
+            wave_lds_sync();
         }
         if (FLUCT && fl && lane == 0) flags[gsub] = (uint8_t)fl;
     }
