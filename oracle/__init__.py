@@ -80,6 +80,12 @@ def lib():
         L.lo_stream_uniforms.restype = None
         L.lo_conv_direct.argtypes = [_c.c_int] * 7 + [_pd, _pd, _pd]
         L.lo_conv_direct.restype = None
+        L.lo_fc.argtypes = [_c.c_double]
+        L.lo_fc.restype = _c.c_double
+        L.lo_btrd_log_accept.argtypes = [_c.c_double] * 4
+        L.lo_btrd_log_accept.restype = _c.c_int
+        L.lo_ptrs_log_accept.argtypes = [_c.c_double] * 4
+        L.lo_ptrs_log_accept.restype = _c.c_int
         _lib = L
     return _lib
 
@@ -159,6 +165,22 @@ def stream_uniforms(seed, depo, event, bin_, plane, count):
     out = np.zeros(count)
     lib().lo_stream_uniforms(int(seed), int(depo), int(event), int(bin_), int(plane), int(count), out)
     return out
+
+
+def stirling_tail(k):
+    """The samplers' fc(k) = log k! - [(k+1/2) log(k+1) - (k+1) + log(2 pi)/2]."""
+    return lib().lo_fc(float(k))
+
+
+def btrd_log_accept(n, p, k, v):
+    """BTRD's decision for a try at k far from the mode (|k - m| > 15) with
+    rescaled uniform v: True to accept (log v <= log f(k)/f(m))."""
+    return bool(lib().lo_btrd_log_accept(float(n), float(p), float(k), float(v)))
+
+
+def ptrs_log_accept(lam, us, v, k):
+    """PTRS's final decision for candidate k with us = 1/2 - |u| and uniform v."""
+    return bool(lib().lo_ptrs_log_accept(float(lam), float(us), float(v), float(k)))
 
 
 def sample_counts(mode, q, p, ctr3, plane_id, seed):

@@ -228,7 +228,7 @@ static double lo_uniform(lo_stream *s)
 
 /* log(k!) - [(k + 1/2) log(k+1) - (k+1) + log(2 pi)/2]: exact via lgamma for
  * small k, Stirling series (three terms) above. */
-static double lo_fc(double k)
+double lo_fc(double k)
 {
     if (k < 10.0)
         return lgamma(k + 1.0) - (k + 0.5) * log(k + 1.0) + (k + 1.0)
@@ -274,6 +274,24 @@ static double lo_binom_inv(double n, double p, lo_stream *s)
         }
     }
     return floor(n * p);
+}
+
+/* BTRD's test for a try far from the mode (|k - m| > 15): accept when
+ * log v <= log f(k) - log f(m), first through the squeeze bounds t -+ rho of
+ * that log ratio, then through its Stirling form with the corrections fc. */
+static int lo_btrd_log_test(double v, double k, double n, double m, double r, double npq)
+{
+    double km = fabs(k - m);
+    v = log(v);                               /* squeeze on log scale */
+    double rho = (km / npq) * (((km / 3.0 + 0.625) * km + 1.0 / 6.0) / npq + 0.5);
+    double t = -km * km / (2.0 * npq);
+    if (v < t - rho) return 1;
+    if (v > t + rho) return 0;
+    double nm = n - m + 1.0;
+    double h = (m + 0.5) * log((m + 1.0) / (r * nm)) + lo_fc(m) + lo_fc(n - m);
+    double nk = n - k + 1.0;
+    return v <= h + (n + 1.0) * log(nm / nk) + (k + 0.5) * log(nk * r / (k + 1.0))
+                - lo_fc(k) - lo_fc(n - k);
 }
 
 /* Binomial(n, p) by BTRD (p <= 1/2, n*p >= 10). */
@@ -324,19 +342,20 @@ static double lo_binom_btrd(double n, double p, lo_stream *s)
             }
             continue;
         }
-        v = log(v);                               /* squeeze on log scale */
-        double rho = (km / npq) * (((km / 3.0 + 0.625) * km + 1.0 / 6.0) / npq + 0.5);
-        double t = -km * km / (2.0 * npq);
-        if (v < t - rho) return k;
-        if (v > t + rho) continue;
-        double nm = n - m + 1.0;
-        double h = (m + 0.5) * log((m + 1.0) / (r * nm)) + lo_fc(m) + lo_fc(n - m);
-        double nk = n - k + 1.0;
-        if (v <= h + (n + 1.0) * log(nm / nk) + (k + 0.5) * log(nk * r / (k + 1.0))
-                  - lo_fc(k) - lo_fc(n - k))
-            return k;
+        if (lo_btrd_log_test(v, k, n, m, r, npq)) return k;
     }
     return m;
+}
+
+/* BTRD's acceptance decision for a try with |k - m| > 15 (v: the try's
+ * rescaled uniform), without the standalone setup of lo_binom_btrd; exported
+ * so that tests can compare it with the exact pmf ratio. */
+int lo_btrd_log_accept(double n, double p, double k, double v)
+{
+    double m = floor((n + 1.0) * p);
+    double r = p / (1.0 - p);
+    double npq = n * p * (1.0 - p);
+    return lo_btrd_log_test(v, k, n, m, r, npq);
 }
 
 /* Binomial(n, p) for any p in [0, 1]. */
@@ -348,6 +367,14 @@ double lo_binomial(double n, double p, lo_stream *s)
     double pp = flip ? 1.0 - p : p;
     double k = (n * pp < 10.0) ? lo_binom_inv(n, pp, s) : lo_binom_btrd(n, pp, s);
     return flip ? n - k : k;
+}
+
+/* PTRS's final test: accept k when v, rescaled by the hat function at u
+ * (alpha / (a/us^2 + b)), lies below the Poisson pmf at k, on a log scale. */
+static int lo_ptrs_log_test(double lam, double loglam, double a, double b, double invalpha,
+                            double us, double v, double k)
+{
+    return log(v) + log(invalpha) - log(a / (us * us) + b) <= -lam + k * loglam - lgamma(k + 1.0);
 }
 
 /* Poisson(lambda): inversion below 10, PTRS above. */
@@ -382,11 +409,20 @@ double lo_poisson(double lam, lo_stream *s)
         double k = floor((2.0 * a / us + b) * u + lam + 0.43);
         if (us >= 0.07 && v <= vr) return k;
         if (k < 0.0 || (us < 0.013 && v > us)) continue;
-        if (log(v) + log(invalpha) - log(a / (us * us) + b)
-            <= -lam + k * loglam - lgamma(k + 1.0))
-            return k;
+        if (lo_ptrs_log_test(lam, loglam, a, b, invalpha, us, v, k)) return k;
     }
     return floor(lam);
+}
+
+/* PTRS's final acceptance decision for candidate k from (u, v), lam >= 10,
+ * with PTRS's setup constants; exported so that tests can compare it with
+ * the exact Poisson pmf. */
+int lo_ptrs_log_accept(double lam, double us, double v, double k)
+{
+    double b = 0.931 + 2.53 * sqrt(lam);
+    double a = -0.059 + 0.02483 * b;
+    double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+    return lo_ptrs_log_test(lam, log(lam), a, b, invalpha, us, v, k);
 }
 
 /* Signed fluctuated count for one bin: sign(q) * n with n drawn for
