@@ -17,6 +17,11 @@ Contents (paper arXiv:2203.02479):
 * ``conv_direct`` -- Eq. (1) first term as a brute-force sum (tiny sizes).
 * ``conv_adjoint`` -- gradients of <M, G> with respect to the grid and the
   complex response spectrum.
+* ``sample_counts`` mode 3 -- the normal approximation of the binomial that
+  the paper's GPU port uses (Sec. 3.1).
+* ``stages.drift`` / ``drift_adjoint`` -- the drift stage upstream of the
+  raster (Sec. 2.2); ``stages.noise`` / ``digitize`` -- the noise term of
+  Eq. (1) and the ADC downstream of the convolution.
 
 Conventions fixed where the paper is silent: the time axis is circular over
 the FFT length Tf (ticks >= n_ticks hold zero charge), the wire axis circular
@@ -80,6 +85,9 @@ def lib():
         L.lo_stream_uniforms.restype = None
         L.lo_conv_direct.argtypes = [_c.c_int] * 7 + [_pd, _pd, _pd]
         L.lo_conv_direct.restype = None
+        L.lo_box_muller.argtypes = [_c.c_double, _c.c_double, _c.POINTER(_c.c_double),
+                                    _c.POINTER(_c.c_double)]
+        L.lo_box_muller.restype = None
         L.lo_fc.argtypes = [_c.c_double]
         L.lo_fc.restype = _c.c_double
         L.lo_btrd_log_accept.argtypes = [_c.c_double] * 4
@@ -183,8 +191,16 @@ def ptrs_log_accept(lam, us, v, k):
     return bool(lib().lo_ptrs_log_accept(float(lam), float(us), float(v), float(k)))
 
 
+def box_muller(u1, u2):
+    """(sqrt(-2 log u1) cos(2 pi u2), sqrt(-2 log u1) sin(2 pi u2))."""
+    c, s = _c.c_double(0.0), _c.c_double(0.0)
+    lib().lo_box_muller(float(u1), float(u2), _c.byref(c), _c.byref(s))
+    return c.value, s.value
+
+
 def sample_counts(mode, q, p, ctr3, plane_id, seed):
-    """Signed per-bin counts for injected (q, p, counter) triples.
+    """Signed per-bin counts for injected (q, p, counter) triples: mode 1
+    binomial, 2 Poisson, 3 normal approximation of the binomial.
     ctr3 is uint32 [n][3] = (depo, event, bin)."""
     q = _f32(q)
     p = np.ascontiguousarray(p, dtype=np.float64)
@@ -282,3 +298,7 @@ def conv_direct(plane, r_time, S):
 def sim_plane_mean(plane, depos, resp, nsigma=3.0):
     """Mean-path waveforms of one plane: conv_fft(raster_mean(...))."""
     return conv_fft(plane, raster_mean(plane, depos, nsigma), resp)
+
+
+from .stages import (digitize, drift, drift_adjoint, noise, noise_digitize,  # noqa: E402
+                     noise_normals, noise_spectrum)

@@ -29,6 +29,11 @@
  *    generation of binomial random variates").
  *    Poisson: inversion when lambda < 10, else PTRS (Hormann 1993, "The
  *    transformed rejection method for generating Poisson random variables").
+ *    Mode 3: the normal approximation of the binomial (Sec. 3.1), rounded
+ *    to the nearest integer and clipped to [0, rint|q|].
+ *  - Noise normals: Gaussian pairs per (wire, frequency) for the noise term
+ *    N(t,x) of Eq. (1), from the same Philox stream layout in its own
+ *    counter domain.
  *  - Adjoint raster: gradients of sum(G*S) with respect to q, t, x, sigma_t,
  *    sigma_x with the windows held fixed.
  *  - Brute-force convolution: M[w][t] = sum_k sum_dw sum_tau
@@ -425,15 +430,49 @@ int lo_ptrs_log_accept(double lam, double us, double v, double k)
     return lo_ptrs_log_test(lam, log(lam), a, b, invalpha, us, v, k);
 }
 
+/* Standard normal deviates from two uniforms (Box and Muller 1958): the
+ * cosine branch sqrt(-2 log u1) cos(2 pi u2) and the sine branch. */
+void lo_box_muller(double u1, double u2, double *z_cos, double *z_sin)
+{
+    double r = sqrt(-2.0 * log(u1));
+    double a = 6.283185307179586 * u2;
+    *z_cos = r * cos(a);
+    if (z_sin) *z_sin = r * sin(a);
+}
+
+/* Normal approximation of Binomial(n, p) (the GPU port's choice, Sec. 3.1):
+ * mu = n p, sd = sqrt(mu (1 - p)), count = mu + sd z rounded to the nearest
+ * integer (ties to even) and clipped to [0, n], with z the cosine branch of
+ * Box-Muller on the bin's first two uniforms. */
+double lo_binomial_normal(double n, double p, lo_stream *s)
+{
+    if (!(n > 0.0) || !(p > 0.0)) return 0.0;
+    if (p >= 1.0) return n;
+    double u1 = lo_uniform(s);
+    double u2 = lo_uniform(s);
+    double z;
+    lo_box_muller(u1, u2, &z, NULL);
+    double mu = n * p;
+    double sd = sqrt(mu * (1.0 - p));
+    double k = rint(mu + sd * z);
+    if (k < 0.0) k = 0.0;
+    if (k > n) k = n;
+    return k;
+}
+
 /* Signed fluctuated count for one bin: sign(q) * n with n drawn for
- * mode 1 = Binomial(rint|q|, p), mode 2 = Poisson(|q| p). */
+ * mode 1 = Binomial(rint|q|, p), mode 2 = Poisson(|q| p), mode 3 = the
+ * normal approximation of Binomial(rint|q|, p). */
 double lo_bin_count(int mode, float q, double p, uint64_t seed, uint32_t depo,
                     uint32_t event, uint32_t bin, uint32_t plane)
 {
     lo_stream s;
     lo_stream_init(&s, seed, depo, event, bin, plane);
     double aq = fabs((double)q);
-    double n = (mode == 1) ? lo_binomial(rint(aq), p, &s) : lo_poisson(aq * p, &s);
+    double n;
+    if (mode == 1) n = lo_binomial(rint(aq), p, &s);
+    else if (mode == 2) n = lo_poisson(aq * p, &s);
+    else n = lo_binomial_normal(rint(aq), p, &s);
     return q < 0.0f ? -n : n;
 }
 
@@ -444,6 +483,25 @@ void lo_sample_counts(int mode, int64_t n, const float *q, const double *p,
     for (int64_t i = 0; i < n; ++i)
         out[i] = lo_bin_count(mode, q[i], p[i], seed, ctr3[3 * i], ctr3[3 * i + 1],
                               ctr3[3 * i + 2], plane);
+}
+
+/* Gaussian pairs of the noise term (Eq. (1) second term): for wire w and
+ * frequency bin f, one Philox block with counter (w, event, f, plane*2^24 +
+ * 2^23) -- bit 23 of the last word marks the noise domain, which the raster's
+ * draw index never reaches -- gives two uniforms and Box-Muller's cosine and
+ * sine branches, written to re[w*nf + f] and im[w*nf + f]. */
+void lo_noise_normals(uint64_t seed, uint32_t event, uint32_t plane, int n_wires, int nf,
+                      double *re, double *im)
+{
+    for (int w = 0; w < n_wires; ++w)
+        for (int f = 0; f < nf; ++f) {
+            lo_stream s;
+            lo_stream_init(&s, seed, (uint32_t)w, event, (uint32_t)f, plane);
+            s.ctr[3] += 0x00800000u;
+            double u1 = lo_uniform(&s);
+            double u2 = lo_uniform(&s);
+            lo_box_muller(u1, u2, &re[(size_t)w * nf + f], &im[(size_t)w * nf + f]);
+        }
 }
 
 /* Raw uniforms of one stream, for tests of the stream layout. */
