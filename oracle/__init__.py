@@ -13,7 +13,7 @@ Contents (paper arXiv:2203.02479):
   fluctuation (Sec. 3.1: the reference code samples a binomial).
 * ``response_spectrum`` / ``conv_fft`` -- the frequency-domain convolution of
   Sec. 2.2 Eq. (2): FT of the charge grid, product with the response
-  spectrum, inverse FT, with numpy's FFT as the transform step.
+  spectrum, inverse FT, with scipy's FFT (pocketfft) as the transform step.
 * ``conv_direct`` -- Eq. (1) first term as a brute-force sum (tiny sizes).
 * ``conv_adjoint`` -- gradients of <M, G> with respect to the grid and the
   complex response spectrum.
@@ -36,11 +36,13 @@ import os
 import subprocess
 
 import numpy as np
+import scipy.fft as sfft
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lar_oracle.c")
 _SO = os.path.join(_HERE, "liblar_oracle.so")
 _lib = None
+_THREADS = 1          # threads of the C depo loops and of the FFT steps
 
 _c = ctypes
 _pf = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
@@ -52,7 +54,7 @@ def build(force: bool = False) -> str:
     """Compile the C part of the oracle (gcc, -O2, no contraction)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -88,6 +90,9 @@ def lib():
         L.lo_box_muller.argtypes = [_c.c_double, _c.c_double, _c.POINTER(_c.c_double),
                                     _c.POINTER(_c.c_double)]
         L.lo_box_muller.restype = None
+        L.lo_set_threads.argtypes = [_c.c_int]
+        L.lo_set_threads.restype = _c.c_int
+        L.lo_set_threads(_THREADS)
         L.lo_fc.argtypes = [_c.c_double]
         L.lo_fc.restype = _c.c_double
         L.lo_btrd_log_accept.argtypes = [_c.c_double] * 4
@@ -96,6 +101,15 @@ def lib():
         L.lo_ptrs_log_accept.restype = _c.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads for the oracle's depo loops (OpenMP) and FFT steps (scipy's
+    pocketfft workers); 1 by default.  Only the order of FP64 sums changes."""
+    global _THREADS
+    _THREADS = max(1, int(n))
+    lib().lo_set_threads(_THREADS)
+    return _THREADS
 
 
 def _f32(a):
@@ -236,16 +250,18 @@ def response_spectrum(plane, r_time):
 
 def _rfft2(plane, A):
     """rfft over time (length Tf) then FFT over wire (length Wf), zero padded."""
-    return np.fft.fft(np.fft.rfft(A, n=plane.nt_fft, axis=-1), n=plane.nw_fft, axis=-2)
+    w = _THREADS
+    return sfft.fft(sfft.rfft(A, n=plane.nt_fft, axis=-1, workers=w), n=plane.nw_fft, axis=-2, workers=w)
 
 
 def _irfft2_crop(plane, X):
     """Inverse FFT over wire, keep the first n_wires rows, real inverse over
     time with the DC and Nyquist columns taken as real, crop to n_ticks."""
-    Y = np.fft.ifft(X, axis=-2)[..., :plane.n_wires, :].copy()
+    w = _THREADS
+    Y = sfft.ifft(X, axis=-2, workers=w)[..., :plane.n_wires, :].copy()
     Y[..., 0] = Y[..., 0].real
     Y[..., -1] = Y[..., -1].real
-    return np.fft.irfft(Y, n=plane.nt_fft, axis=-1)[..., :plane.n_ticks]
+    return sfft.irfft(Y, n=plane.nt_fft, axis=-1, workers=w)[..., :plane.n_ticks]
 
 
 def sub_grids(plane, S):

@@ -7,7 +7,7 @@
  * call this file; it exists so that tests and the benchmark's CPU-baseline
  * leg can check the GPU path against a direct transcription of the
  * definitions.  It shares no code, header, table or constant with the GPU
- * library.  Build: gcc -O2 -ffp-contract=off -fPIC -shared -lm.
+ * library.  Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared -lm.
  *
  * What it computes (paper Sec. 2.1 Eq. (1) first term; Sec. 2.2 "Raster",
  * "Scatter-add"; Sec. 3.1 binomial fluctuation of the reference code):
@@ -42,9 +42,14 @@
  *    axes over the FFT lengths, exactly what the FFT product computes).
  *
  * All floating point is FP64 with contraction off; inputs are the float32
- * arrays the GPU receives, widened exactly.
+ * arrays the GPU receives, widened exactly.  The loops over depositions run
+ * on OpenMP threads (lo_set_threads; 1 by default): each thread takes whole
+ * depositions and adds to the shared grid with atomic updates, so only the
+ * order of the FP64 sums depends on the thread count (fluctuated counts are
+ * integers and sum exactly).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -146,20 +151,40 @@ int lo_raster_mean(int n_wires, int n_imp, int n_ticks, double pitch, double x0,
                    const float *st, const float *sx, double *grid)
 {
     int n_rows = n_wires * n_imp;
-    lo_patch P;
-    if (lo_alloc_patch(&P, n_ticks, n_rows)) return -1;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
-        if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
-                           t[i], x[i], st[i], sx[i], &P, 0)) continue;
-        double qi = q[i];
-        for (int a = 0; a < P.nx; ++a) {
-            double *row = grid + (size_t)(P.mlo + a) * n_ticks + P.jlo;
-            for (int b = 0; b < P.nt; ++b) row[b] += qi * P.wt[b] * P.wx[a];
+    int failed = 0;
+#pragma omp parallel reduction(| : failed)
+    {
+        lo_patch P;
+        if (lo_alloc_patch(&P, n_ticks, n_rows)) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < n; ++i) {
+                if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
+                if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
+                                   t[i], x[i], st[i], sx[i], &P, 0)) continue;
+                double qi = q[i];
+                for (int a = 0; a < P.nx; ++a) {
+                    double *row = grid + (size_t)(P.mlo + a) * n_ticks + P.jlo;
+                    for (int b = 0; b < P.nt; ++b) {
+                        double v = qi * P.wt[b] * P.wx[a];
+#pragma omp atomic
+                        row[b] += v;
+                    }
+                }
+            }
+            lo_free_patch(&P);
         }
     }
-    lo_free_patch(&P);
-    return 0;
+    return failed ? -1 : 0;
+}
+
+/* Threads of the depo loops (omp_set_num_threads); returns the count set. */
+int lo_set_threads(int n)
+{
+    if (n < 1) n = 1;
+    omp_set_num_threads(n);
+    return n;
 }
 
 /* ------------------------------------------------------------ Philox4x32-10 */
@@ -521,25 +546,34 @@ int lo_raster_fluct(int n_wires, int n_imp, int n_ticks, double pitch, double x0
                     uint32_t event, uint32_t plane, double *grid)
 {
     int n_rows = n_wires * n_imp;
-    lo_patch P;
-    if (lo_alloc_patch(&P, n_ticks, n_rows)) return -1;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
-        if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
-                           t[i], x[i], st[i], sx[i], &P, 0)) continue;
-        for (int a = 0; a < P.nx; ++a) {
-            int m = P.mlo + a;
-            for (int b = 0; b < P.nt; ++b) {
-                int j = P.jlo + b;
-                double p = P.wt[b] * P.wx[a];
-                uint32_t bin = (uint32_t)((int64_t)m * n_ticks + j);
-                grid[(size_t)m * n_ticks + j] +=
-                    lo_bin_count(mode, q[i], p, seed, (uint32_t)i, event, bin, plane);
+    int failed = 0;
+#pragma omp parallel reduction(| : failed)
+    {
+        lo_patch P;
+        if (lo_alloc_patch(&P, n_ticks, n_rows)) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < n; ++i) {
+                if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
+                if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
+                                   t[i], x[i], st[i], sx[i], &P, 0)) continue;
+                for (int a = 0; a < P.nx; ++a) {
+                    int m = P.mlo + a;
+                    for (int b = 0; b < P.nt; ++b) {
+                        int j = P.jlo + b;
+                        double p = P.wt[b] * P.wx[a];
+                        uint32_t bin = (uint32_t)((int64_t)m * n_ticks + j);
+                        double c = lo_bin_count(mode, q[i], p, seed, (uint32_t)i, event, bin, plane);
+#pragma omp atomic
+                        grid[(size_t)m * n_ticks + j] += c;
+                    }
+                }
             }
+            lo_free_patch(&P);
         }
     }
-    lo_free_patch(&P);
-    return 0;
+    return failed ? -1 : 0;
 }
 
 /* ------------------------------------------------------------ adjoint raster */
@@ -553,34 +587,42 @@ int lo_raster_adjoint(int n_wires, int n_imp, int n_ticks, double pitch, double 
                       double *dq, double *dt, double *dx, double *dst, double *dsx)
 {
     int n_rows = n_wires * n_imp;
-    lo_patch P;
-    if (lo_alloc_patch(&P, n_ticks, n_rows)) return -1;
-    for (int64_t i = 0; i < n; ++i) {
-        dq[i] = dt[i] = dx[i] = dst[i] = dsx[i] = 0.0;
-        if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
-        if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
-                           t[i], x[i], st[i], sx[i], &P, 1)) continue;
-        double s_q = 0, s_t = 0, s_st = 0, s_x = 0, s_sx = 0;
-        for (int a = 0; a < P.nx; ++a) {
-            const double *row = G + (size_t)(P.mlo + a) * n_ticks + P.jlo;
-            for (int b = 0; b < P.nt; ++b) {
-                double g = row[b];
-                s_q += g * P.wt[b] * P.wx[a];
-                s_t += g * P.dwt_dmu[b] * P.wx[a];
-                s_st += g * P.dwt_ds[b] * P.wx[a];
-                s_x += g * P.wt[b] * P.dwx_dmu[a];
-                s_sx += g * P.wt[b] * P.dwx_ds[a];
+    int failed = 0;
+#pragma omp parallel reduction(| : failed)
+    {
+        lo_patch P;
+        if (lo_alloc_patch(&P, n_ticks, n_rows)) {
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < n; ++i) {
+                dq[i] = dt[i] = dx[i] = dst[i] = dsx[i] = 0.0;
+                if (!lo_finite5(q[i], t[i], x[i], st[i], sx[i])) continue;
+                if (!lo_make_patch(n_rows, n_ticks, pitch, x0, n_imp, tick, t0, nsig,
+                                   t[i], x[i], st[i], sx[i], &P, 1)) continue;
+                double s_q = 0, s_t = 0, s_st = 0, s_x = 0, s_sx = 0;
+                for (int a = 0; a < P.nx; ++a) {
+                    const double *row = G + (size_t)(P.mlo + a) * n_ticks + P.jlo;
+                    for (int b = 0; b < P.nt; ++b) {
+                        double g = row[b];
+                        s_q += g * P.wt[b] * P.wx[a];
+                        s_t += g * P.dwt_dmu[b] * P.wx[a];
+                        s_st += g * P.dwt_ds[b] * P.wx[a];
+                        s_x += g * P.wt[b] * P.dwx_dmu[a];
+                        s_sx += g * P.wt[b] * P.dwx_ds[a];
+                    }
+                }
+                double qi = q[i];
+                dq[i] = s_q;
+                dt[i] = qi * s_t;
+                dst[i] = qi * s_st;
+                dx[i] = qi * s_x;
+                dsx[i] = qi * s_sx;
             }
+            lo_free_patch(&P);
         }
-        double qi = q[i];
-        dq[i] = s_q;
-        dt[i] = qi * s_t;
-        dst[i] = qi * s_st;
-        dx[i] = qi * s_x;
-        dsx[i] = qi * s_sx;
     }
-    lo_free_patch(&P);
-    return 0;
+    return failed ? -1 : 0;
 }
 
 /* ------------------------------------------------------------ direct convolution */
