@@ -78,11 +78,16 @@ typedef struct lar_depos {
 } lar_depos;
 
 /* Charge fluctuation (paper Sec. 3.1: the reference code draws binomial
- * electron counts).  mode 0: mean patch q*wt*wx; 1: Binomial(rint|q|, p)
- * per bin; 2: Poisson(|q| p) per bin; p = wt*wx, sign(q) restored.  Draws
+ * electron counts, the GPU port a normal approximation).  mode 0: mean
+ * patch q*wt*wx; 1: Binomial(rint|q|, p) per bin; 2: Poisson(|q| p) per
+ * bin; 3: the normal approximation of mode 1, rint(n p + sqrt(n p (1-p)) z)
+ * clipped to [0, n], n = rint|q|, z = sqrt(-2 log u1) cos(2 pi u2) from the
+ * bin's first two uniforms; p = wt*wx, sign(q) restored.  Draws
  * use Philox4x32-10 with key = seed and counter (depo index, event,
  * m*n_ticks + j, plane*2^24 + draw), so results are reproducible for any
- * launch shape.  NULL = mode 0. */
+ * launch shape.  NULL = mode 0.  plane < 256; with mode != 0 the grid's
+ * n_wires*n_imp*n_ticks must not exceed 2^32 - 1 (the bin word), else
+ * LAR_ESIZE. */
 typedef struct lar_fluct {
     int32_t mode;
     uint32_t event;
@@ -110,7 +115,8 @@ int lar_last_hip_error(void);
  * at least the size it gives for n_depos = depos->n with a queue of zero
  * (the sum of a 256-byte header and one byte per 16 depos, rounded up to
  * 256) is accepted and gives the same counts, a smaller queue only moves
- * work to a slower path.  The workspace must be 256-byte aligned. */
+ * work to a slower path (mode 3 queues nothing: the header and flags are
+ * all it needs).  The workspace must be 256-byte aligned. */
 int lar_raster_workspace(const lar_plane *plane, int64_t n_depos, const lar_fluct *fluct,
                          size_t *bytes);
 int lar_raster(const lar_plane *plane, const lar_depos *depos, float nsigma,
@@ -154,12 +160,13 @@ int lar_fftconv_backward(const lar_plane *plane, const float *grid, const float 
  * over ticks of every grid row, [n_wires*n_imp][ld] complex64 (float
  * pairs), ld = nt_fft/2 + 1 rounded up to a multiple of 16.  Keeping that
  * workspace for the backward pass saves the transform of the grid.
- * grid_spec is overwritten (it holds the grid-gradient spectrum) when
- * grid_grad is given.  resp_accumulate != 0: resp_grad += gradient, as in
- * lar_fftconv_backward; 0: resp_grad = gradient.  Workspace: the FT of
- * wave_grad (lar_fftconv_backward_spec_workspace). */
+ * grid_spec is only read, so the same spectrum serves any number of
+ * backward calls.  resp_accumulate != 0: resp_grad += gradient, as in
+ * lar_fftconv_backward; 0: resp_grad = gradient.  Workspace
+ * (lar_fftconv_backward_spec_workspace): the FT of wave_grad and the
+ * grid-gradient spectrum. */
 int lar_fftconv_backward_spec_workspace(const lar_plane *plane, size_t *bytes);
-int lar_fftconv_backward_spec(const lar_plane *plane, void *grid_spec, const float *resp,
+int lar_fftconv_backward_spec(const lar_plane *plane, const void *grid_spec, const float *resp,
                               const float *wave_grad, float *grid_grad, float *resp_grad,
                               int32_t resp_accumulate, void *workspace, size_t ws_bytes,
                               void *stream);
@@ -186,12 +193,86 @@ int lar_response_spectrum(const lar_plane *plane, const float *r_time, int32_t h
                           void *stream);
 
 /* The per-bin sampler of lar_raster on injected inputs (same device code):
- * out[i] = sign(q[i]) * n with n ~ Binomial(rint|q[i]|, p[i]) (mode 1) or
- * Poisson(|q[i]| p[i]) (mode 2), counter (ctr3[3i], ctr3[3i+1], ctr3[3i+2],
+ * out[i] = sign(q[i]) * n with n ~ Binomial(rint|q[i]|, p[i]) (mode 1),
+ * Poisson(|q[i]| p[i]) (mode 2) or the normal approximation of the
+ * binomial (mode 3), counter (ctr3[3i], ctr3[3i+1], ctr3[3i+2],
  * plane*2^24 + draw), key = seed.  p is double (the sampler's precision). */
 int lar_sample_counts(int32_t mode, int64_t n, const float *q, const double *p,
                       const uint32_t *ctr3, uint32_t plane, uint64_t seed, float *out,
                       void *stream);
+
+/* ---------------------------------------------------------------- drift
+ * The drift of ionization groups to the anode, upstream of the raster
+ * (paper Sec. 2.2: a group is diffused while it drifts, so it reaches the
+ * wires as a 2D Gaussian over drift time and wire pitch).  Per group, in
+ * FP64 from the float32 inputs, each output rounded once to float32:
+ *   td = max(xd, 0) / speed                      (drift time, us)
+ *   q  = q0 * exp(-td / lifetime)                (lifetime <= 0: q = q0)
+ *   t  = t0 + td,  sigma_t = sqrt(2 diff_l td) / speed  (time units),
+ *   sigma_x = sqrt(2 diff_t td),
+ *   x[p] = z * proj[p].cos + y * proj[p].sin + proj[p].offset
+ * for each of the n_planes wire planes (the pitch coordinate on plane p).
+ * Units: mm, us, electrons.  The outputs form the lar_depos of each plane
+ * (q, t, x[p], sigma_t, sigma_x). */
+typedef struct lar_drift_params {
+    float speed;      /* drift speed v (mm/us), > 0 */
+    float diff_l;     /* longitudinal diffusion constant D_L (mm^2/us), >= 0 */
+    float diff_t;     /* transverse diffusion constant D_T (mm^2/us), >= 0 */
+    float lifetime;   /* electron lifetime (us); <= 0 means no attenuation */
+} lar_drift_params;
+
+typedef struct lar_plane_proj {
+    float cos_a, sin_a, offset;   /* x = z cos_a + y sin_a + offset (mm) */
+} lar_plane_proj;
+
+/* Inputs (device, n floats each): q0 (electrons at creation), t0 (creation
+ * time, us), xd (distance to the anode along the drift, mm), y, z (mm).
+ * proj: n_planes entries in HOST memory, 0 <= n_planes <= 8.  Outputs
+ * (device, OVERWRITTEN): q, t, sigma_t, sigma_x (n floats each) and x
+ * ([n_planes][n] floats; may be NULL when n_planes = 0).  No workspace. */
+int lar_drift(const lar_drift_params *prm, const float *q0, const float *t0, const float *xd,
+              const float *y, const float *z, int64_t n, const lar_plane_proj *proj,
+              int32_t n_planes, float *q, float *t, float *sigma_t, float *sigma_x, float *x,
+              void *stream);
+
+/* Adjoint of lar_drift (no paper counterpart): gradients of
+ * L = sum(gq q + gt t + gsigma_t sigma_t + gsigma_x sigma_x + sum_p gx[p] x[p])
+ * with respect to the inputs (dq0, dt0, dxd, dy, dz: n floats each,
+ * OVERWRITTEN, each may be NULL) and to the four parameters (dparams: 4
+ * floats (speed, diff_l, diff_t, lifetime), OVERWRITTEN, may be NULL),
+ * summed over the groups in a fixed order (deterministic).  Where xd <= 0,
+ * or a width is zero, the derivative terms through td or through that
+ * width's square root are zero.  gx: [n_planes][n] (may be NULL when
+ * n_planes = 0).  Workspace (for dparams): lar_drift_backward_workspace. */
+int lar_drift_backward_workspace(int64_t n, size_t *bytes);
+int lar_drift_backward(const lar_drift_params *prm, const float *q0, const float *xd, int64_t n,
+                       const lar_plane_proj *proj, int32_t n_planes, const float *gq,
+                       const float *gt, const float *gsigma_t, const float *gsigma_x,
+                       const float *gx, float *dq0, float *dt0, float *dxd, float *dy, float *dz,
+                       float *dparams, void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- noise, ADC
+ * The noise term N(t,x) of Eq. (1) (paper Sec. 2.1; Sec. 2.2 leaves it out
+ * of the port) and the digitisation downstream of the convolution.
+ * lar_noise: per wire w < n_wires a random half spectrum
+ *   X[w][f] = amp[f] (g_re + i g_im),  f <= nt_fft/2,
+ * with (g_re, g_im) the Box-Muller cosine and sine normals of the two
+ * uniforms of Philox4x32-10 block (w, event, f, plane*2^24 + 2^23), key =
+ * seed (bit 23 of the last word keeps it apart from the raster's draws);
+ * the DC and Nyquist bins are real.  noise = the inverse real FFT over
+ * nt_fft (1/nt_fft) cropped to [n_wires][n_ticks], OVERWRITTEN.  amp:
+ * nt_fft/2 + 1 floats (device).  plane < 256.  Workspace:
+ * lar_noise_workspace. */
+int lar_noise_workspace(const lar_plane *plane, size_t *bytes);
+int lar_noise(const lar_plane *plane, const float *amp, uint64_t seed, uint32_t event,
+              uint32_t plane_id, float *noise, void *workspace, size_t ws_bytes, void *stream);
+
+/* ADC codes: adc[i] = clip(rint(gain * v + baseline), 0, 2^bits - 1) with
+ * v = wave[i] + noise[i] (noise may be NULL), each operation a float32
+ * operation rounded on its own (no fused multiply-add), rint ties to even,
+ * a NaN voltage gives 0.  1 <= bits <= 16.  n >= 0 elements. */
+int lar_digitize(const float *wave, const float *noise, int64_t n, float gain, float baseline,
+                 int32_t bits, uint16_t *adc, void *stream);
 
 /* ---------------------------------------------------------------- batching
  * Many (event, plane) items in one launch sequence (no paper counterpart:

@@ -58,9 +58,14 @@ int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, in
            const lar_fluct* fluct, Layout& L) {
     if (!planes || n_types < 1 || !items || n_items < 1) return LAR_EINVAL;
     if (n_items >= (1 << 27)) return LAR_ESIZE;   // item index shares a 32-bit word with queue marks
-    if (fluct && (fluct->mode < 0 || fluct->mode > 2)) return LAR_EINVAL;
-    for (int t = 0; t < n_types; ++t)
+    if (fluct && (fluct->mode < 0 || fluct->mode > 3)) return LAR_EINVAL;
+    for (int t = 0; t < n_types; ++t) {
         if (!plane_ok(planes[t])) return LAR_ESIZE;
+        // a drawn bin's counter word is m * n_ticks + j
+        if (fluct && fluct->mode != 0 &&
+            (int64_t)planes[t].n_wires * planes[t].n_imp * planes[t].n_ticks > (int64_t)UINT32_MAX)
+            return LAR_ESIZE;
+    }
     L.type_count.assign(n_types, 0);
     int64_t total_depos = 0;
     for (int i = 0; i < n_items; ++i) {
@@ -107,7 +112,8 @@ int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, in
     }
     L.raster = off;
     if (fluct && fluct->mode != 0)
-        off += raster_ws_fixed_subs(L.total_sub) + al(((size_t)total_depos * 48 + 4096) * kDeferredBytes);
+        off += raster_ws_fixed_subs(L.total_sub) +
+               (fluct->mode == 3 ? 0 : al(((size_t)total_depos * 48 + 4096) * kDeferredBytes));
     L.total = off;
     return LAR_OK;
 }

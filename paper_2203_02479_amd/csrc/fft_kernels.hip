@@ -525,12 +525,13 @@ hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_im
 //    spectrum rows w*n_imp + k, dR[k] += resp_scale c_f Gh conj(Sk), with
 //    c_f = 1 at f = 0 and f = Tf/2 and 2 elsewhere;
 //  - grid gradient (want_grid): conj(R[k]) Gh, inverse FFT over wires,
-//    written over the same rows of S (each tile reads them first).
+//    written to the rows w*n_imp + k of O.  O may be S itself: each tile
+//    reads its columns of a row of S before it writes them.
 template <int VPT, int C, int NT>
 __global__ __launch_bounds__(NT) void k_wire_adjoint(
-    const float2* __restrict__ Gt, int64_t ldG, float2* __restrict__ S, int64_t ldS, int n_wires,
-    int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R, float2* __restrict__ dR,
-    int want_grid, float resp_scale, int accumulate) {
+    const float2* __restrict__ Gt, int64_t ldG, const float2* S, int64_t ldS, float2* O, int64_t ldO,
+    int n_wires, int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R,
+    float2* __restrict__ dR, int want_grid, float resp_scale, int accumulate) {
     extern __shared__ float2 lds[];
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
@@ -619,40 +620,42 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
             for (int i = 0; i < VPT; ++i) {
                 const int e = tid + i * T;
                 const int p = e / C, f = f0 + e % C;
-                if (e < nel && p < n_wires && f < F) S[(int64_t)(p * n_imp + k) * ldS + f] = A[e];
+                if (e < nel && p < n_wires && f < F) O[(int64_t)(p * n_imp + k) * ldO + f] = A[e];
             }
         }
     }
 }
 
 template <int VPT, int C, int NT>
-static hipError_t wire_adj_launch(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
-                                  int n_imp, int F, int nyq, const FftPlan& plan, const float2* R,
-                                  float2* dR, bool want_grid, float scale, bool accumulate,
-                                  hipStream_t s) {
+static hipError_t wire_adj_launch(const float2* Gt, int64_t ldG, const float2* S, int64_t ldS,
+                                  float2* O, int64_t ldO, int n_wires, int n_imp, int F, int nyq,
+                                  const FftPlan& plan, const float2* R, float2* dR, bool want_grid,
+                                  float scale, bool accumulate, hipStream_t s) {
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     set_lds(k_wire_adjoint<VPT, C, NT>, lds);
     dim3 grid((F + C - 1) / C), block(NT);
-    hipLaunchKernelGGL((k_wire_adjoint<VPT, C, NT>), grid, block, lds, s, Gt, ldG, S, ldS, n_wires,
-                       n_imp, F, nyq, plan, R, dR, want_grid ? 1 : 0, scale, accumulate ? 1 : 0);
+    hipLaunchKernelGGL((k_wire_adjoint<VPT, C, NT>), grid, block, lds, s, Gt, ldG, S, ldS, O, ldO,
+                       n_wires, n_imp, F, nyq, plan, R, dR, want_grid ? 1 : 0, scale,
+                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
-                               int n_imp, int nw_fft, int nt_fft, const float2* R, float2* dR,
-                               bool want_grid, float resp_scale, hipStream_t s, bool accumulate) {
+hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, const float2* S, int64_t ldS, float2* O,
+                               int64_t ldO, int n_wires, int n_imp, int nw_fft, int nt_fft,
+                               const float2* R, float2* dR, bool want_grid, float resp_scale,
+                               hipStream_t s, bool accumulate) {
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     const int F = nt_fft / 2 + 1, nyq = nt_fft / 2;
-#define LAR_WADJ(V)                                                                              \
-    return wire_adj_launch<V, 8, 512>(Gt, ldG, S, ldS, n_wires, n_imp, F, nyq, plan, R, dR,      \
+#define LAR_WADJ(V)                                                                                   \
+    return wire_adj_launch<V, 8, 512>(Gt, ldG, S, ldS, O, ldO, n_wires, n_imp, F, nyq, plan, R, dR,   \
                                       want_grid, resp_scale, accumulate, s);
     if (nw_fft <= 128) LAR_WADJ(2)
     if (nw_fft <= 256) LAR_WADJ(4)
     if (nw_fft <= 512) LAR_WADJ(8)
     if (nw_fft <= 1024)
-        return wire_adj_launch<8, 8, 1024>(Gt, ldG, S, ldS, n_wires, n_imp, F, nyq, plan, R, dR,
-                                           want_grid, resp_scale, accumulate, s);
+        return wire_adj_launch<8, 8, 1024>(Gt, ldG, S, ldS, O, ldO, n_wires, n_imp, F, nyq, plan, R,
+                                           dR, want_grid, resp_scale, accumulate, s);
 #undef LAR_WADJ
     return hipErrorInvalidValue;
 }

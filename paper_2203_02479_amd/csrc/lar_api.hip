@@ -69,10 +69,13 @@ static int check_depos(const lar_depos* d) {
     return LAR_OK;
 }
 
-static int check_fluct(const lar_fluct* f) {
+static int check_fluct(const lar_fluct* f, const lar_plane* p) {
     if (!f) return LAR_OK;
-    if (f->mode < 0 || f->mode > 2) return LAR_EINVAL;
+    if (f->mode < 0 || f->mode > 3) return LAR_EINVAL;
     if (f->plane >= 256u) return LAR_EINVAL;              // plane * 2^24 must fit one word
+    // a drawn bin's counter word is m * n_ticks + j
+    if (f->mode != 0 && (int64_t)p->n_wires * p->n_imp * p->n_ticks > (int64_t)UINT32_MAX)
+        return LAR_ESIZE;
     return LAR_OK;
 }
 
@@ -114,6 +117,7 @@ static size_t raster_bytes_min(int64_t n, const lar_fluct* f) {
 static size_t raster_bytes(int64_t n, const lar_fluct* f) {
     size_t fixed = raster_bytes_min(n, f);
     if (!fixed) return 0;
+    if (f->mode == 3) return fixed;   // the normal approximation queues nothing
     return fixed + ((size_t)n * 48 + 4096) * kDeferredBytes;
 }
 
@@ -121,7 +125,7 @@ int lar_raster_workspace(const lar_plane* plane, int64_t n_depos, const lar_fluc
                          size_t* bytes) {
     int st;
     if ((st = check_plane(plane))) return st;
-    if ((st = check_fluct(fluct))) return st;
+    if ((st = check_fluct(fluct, plane))) return st;
     if (n_depos < 0 || !bytes) return LAR_EINVAL;
     *bytes = raster_bytes(n_depos, fluct);
     return LAR_OK;
@@ -154,7 +158,7 @@ int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, con
     int st;
     if ((st = check_plane(plane))) return st;
     if ((st = check_depos(depos))) return st;
-    if ((st = check_fluct(fluct))) return st;
+    if ((st = check_fluct(fluct, plane))) return st;
     if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
     if (depos->n == 0) return LAR_OK;
     if (!grid) return LAR_EINVAL;
@@ -222,7 +226,7 @@ int lar_sim_plane_workspace(const lar_plane* plane, int64_t n_depos, const lar_f
                             size_t* bytes) {
     int st;
     if ((st = check_fft(plane))) return st;
-    if ((st = check_fluct(fluct))) return st;
+    if ((st = check_fluct(fluct, plane))) return st;
     if (n_depos < 0 || !bytes) return LAR_EINVAL;
     *bytes = grid_bytes(plane) + fftconv_bytes(plane) + raster_bytes(n_depos, fluct);
     return LAR_OK;
@@ -234,7 +238,7 @@ int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
     int st;
     if ((st = check_fft(plane))) return st;
     if ((st = check_depos(depos))) return st;
-    if ((st = check_fluct(fluct))) return st;
+    if ((st = check_fluct(fluct, plane))) return st;
     if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
     if (!resp || !wave) return LAR_EINVAL;
     const size_t head = grid_bytes(plane) + fftconv_bytes(plane);
@@ -292,7 +296,7 @@ int lar_fftconv_backward(const lar_plane* p, const float* grid, const float* res
     if (resp_grad)
         LAR_TRY(launch_r2c_rows(grid, p->n_ticks, p->n_ticks, rows, p->nt_fft, Sb, ld, s,
                                 sc.row_threads, sc.row_order));
-    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
+    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
                                 reinterpret_cast<const float2*>(resp),
                                 reinterpret_cast<float2*>(resp_grad), grid_grad != nullptr, scale, s));
     if (grid_grad)
@@ -302,8 +306,12 @@ int lar_fftconv_backward(const lar_plane* p, const float* grid, const float* res
 }
 
 // backward from a kept grid spectrum: workspace = the FT of wave_grad only
+// backward from a kept grid spectrum: FT of the waveform gradient, then the
+// grid-gradient spectrum (the kept spectrum is only read)
 static size_t fftconv_bwd_spec_bytes(const lar_plane* p) {
-    return align_up((size_t)p->n_wires * (size_t)spec_ld(p) * sizeof(float2), 256);
+    const size_t ld = (size_t)spec_ld(p);
+    return align_up((size_t)p->n_wires * ld * sizeof(float2), 256) +
+           align_up((size_t)p->n_wires * p->n_imp * ld * sizeof(float2), 256);
 }
 
 int lar_fftconv_backward_spec_workspace(const lar_plane* plane, size_t* bytes) {
@@ -314,7 +322,7 @@ int lar_fftconv_backward_spec_workspace(const lar_plane* plane, size_t* bytes) {
     return LAR_OK;
 }
 
-int lar_fftconv_backward_spec(const lar_plane* p, void* grid_spec, const float* resp,
+int lar_fftconv_backward_spec(const lar_plane* p, const void* grid_spec, const float* resp,
                               const float* wave_grad, float* grid_grad, float* resp_grad,
                               int32_t resp_accumulate, void* ws, size_t ws_bytes, void* stream) {
     int st;
@@ -328,17 +336,19 @@ int lar_fftconv_backward_spec(const lar_plane* p, void* grid_spec, const float* 
     const int64_t ld = spec_ld(p);
     const int rows = p->n_wires * p->n_imp;
     float2* Gt = reinterpret_cast<float2*>(ws);
-    float2* Sb = reinterpret_cast<float2*>(grid_spec);
+    float2* Ob = reinterpret_cast<float2*>(reinterpret_cast<char*>(ws) +
+                                           align_up((size_t)p->n_wires * ld * sizeof(float2), 256));
+    const float2* Sb = reinterpret_cast<const float2*>(grid_spec);
     const float scale = (float)(1.0 / ((double)p->nw_fft * (double)p->nt_fft));
     const Sched sc = sched_of(p);
     LAR_TRY(launch_r2c_rows(wave_grad, p->n_ticks, p->n_ticks, p->n_wires, p->nt_fft, Gt, ld, s,
                             sc.row_threads, sc.row_order));
-    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
+    LAR_TRY(launch_wire_adjoint(Gt, ld, Sb, ld, Ob, ld, p->n_wires, p->n_imp, p->nw_fft, p->nt_fft,
                                 reinterpret_cast<const float2*>(resp),
                                 reinterpret_cast<float2*>(resp_grad), grid_grad != nullptr, scale, s,
                                 resp_accumulate != 0));
     if (grid_grad)
-        LAR_TRY(launch_c2r_rows(Sb, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s,
+        LAR_TRY(launch_c2r_rows(Ob, ld, rows, p->nt_fft, grid_grad, p->n_ticks, p->n_ticks, scale, s,
                                 nullptr, false, sc.row_threads, sc.row_order));
     return LAR_OK;
 }
@@ -403,10 +413,110 @@ int lar_response_spectrum(const lar_plane* plane, const float* r_time, int32_t h
 int lar_sample_counts(int32_t mode, int64_t n, const float* q, const double* p,
                       const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                       void* stream) {
-    if (mode < 1 || mode > 2 || n < 0 || plane >= 256u) return LAR_EINVAL;
+    if (mode < 1 || mode > 3 || n < 0 || plane >= 256u) return LAR_EINVAL;
     if (n == 0) return LAR_OK;
     if (!q || !p || !ctr3 || !out) return LAR_EINVAL;
     LAR_TRY(launch_sample_counts(mode, n, q, p, ctr3, plane, seed, out, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+// ---------------------------------------------------------------- drift, noise, ADC
+
+static int drift_const(const lar_drift_params* prm, const lar_plane_proj* proj, int32_t n_planes,
+                       DriftConst& C) {
+    if (!prm || n_planes < 0 || n_planes > kDriftMaxPlanes || (n_planes > 0 && !proj)) return LAR_EINVAL;
+    if (!(prm->speed > 0.f) || !isfinite(prm->speed) || !(prm->diff_l >= 0.f) || !(prm->diff_t >= 0.f) ||
+        !isfinite(prm->diff_l) || !isfinite(prm->diff_t) || !isfinite(prm->lifetime))
+        return LAR_EINVAL;
+    C.v = (double)prm->speed;
+    C.DL = (double)prm->diff_l;
+    C.DT = (double)prm->diff_t;
+    C.tau = (double)prm->lifetime;
+    C.n_planes = n_planes;
+    for (int p = 0; p < kDriftMaxPlanes; ++p) {
+        const bool on = p < n_planes;
+        C.proj[p][0] = on ? (double)proj[p].cos_a : 0.0;
+        C.proj[p][1] = on ? (double)proj[p].sin_a : 0.0;
+        C.proj[p][2] = on ? (double)proj[p].offset : 0.0;
+    }
+    return LAR_OK;
+}
+
+int lar_drift(const lar_drift_params* prm, const float* q0, const float* t0, const float* xd,
+              const float* y, const float* z, int64_t n, const lar_plane_proj* proj, int32_t n_planes,
+              float* q, float* t, float* sigma_t, float* sigma_x, float* x, void* stream) {
+    DriftConst C;
+    int st;
+    if ((st = drift_const(prm, proj, n_planes, C))) return st;
+    if (n < 0) return LAR_EINVAL;
+    if (n == 0) return LAR_OK;
+    if (!q0 || !t0 || !xd || !y || !z || !q || !t || !sigma_t || !sigma_x || (n_planes > 0 && !x))
+        return LAR_EINVAL;
+    LAR_TRY(launch_drift(C, q0, t0, xd, y, z, n, q, t, sigma_t, sigma_x, x, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+int lar_drift_backward_workspace(int64_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return LAR_EINVAL;
+    *bytes = (size_t)kDriftMaxBlocks * 4 * sizeof(double);
+    return LAR_OK;
+}
+
+int lar_drift_backward(const lar_drift_params* prm, const float* q0, const float* xd, int64_t n,
+                       const lar_plane_proj* proj, int32_t n_planes, const float* gq, const float* gt,
+                       const float* gsigma_t, const float* gsigma_x, const float* gx, float* dq0,
+                       float* dt0, float* dxd, float* dy, float* dz, float* dparams, void* ws,
+                       size_t ws_bytes, void* stream) {
+    DriftConst C;
+    int st;
+    if ((st = drift_const(prm, proj, n_planes, C))) return st;
+    if (n < 0) return LAR_EINVAL;
+    if (dparams && (!ws || ws_bytes < (size_t)kDriftMaxBlocks * 4 * sizeof(double) ||
+                    reinterpret_cast<uintptr_t>(ws) % 256))
+        return LAR_EWORKSPACE;
+    if (n > 0 && (!q0 || !xd || !gq || !gt || !gsigma_t || !gsigma_x || (n_planes > 0 && !gx)))
+        return LAR_EINVAL;
+    LAR_TRY(launch_drift_bwd(C, q0, xd, n, gq, gt, gsigma_t, gsigma_x, gx, dq0, dt0, dxd, dy, dz, dparams,
+                             reinterpret_cast<double*>(ws), (hipStream_t)stream));
+    return LAR_OK;
+}
+
+// noise workspace: the random half spectra [n_wires][ld]
+static size_t noise_bytes(const lar_plane* p) {
+    return align_up((size_t)p->n_wires * (size_t)spec_ld(p) * sizeof(float2), 256);
+}
+
+int lar_noise_workspace(const lar_plane* plane, size_t* bytes) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = noise_bytes(plane);
+    return LAR_OK;
+}
+
+int lar_noise(const lar_plane* p, const float* amp, uint64_t seed, uint32_t event, uint32_t plane_id,
+              float* noise, void* ws, size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(p))) return st;
+    if (!amp || !noise || plane_id >= 256u) return LAR_EINVAL;
+    if (!ws || ws_bytes < noise_bytes(p) || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ld = spec_ld(p);
+    float2* X = reinterpret_cast<float2*>(ws);
+    const Sched sc = sched_of(p);
+    LAR_TRY(launch_noise_spectrum(amp, p->nt_fft / 2 + 1, p->n_wires, seed, event, plane_id, X, ld, s));
+    LAR_TRY(launch_c2r_rows(X, ld, p->n_wires, p->nt_fft, noise, p->n_ticks, p->n_ticks,
+                            (float)(1.0 / (double)p->nt_fft), s, nullptr, false, sc.row_threads,
+                            sc.row_order));
+    return LAR_OK;
+}
+
+int lar_digitize(const float* wave, const float* noise, int64_t n, float gain, float baseline, int32_t bits,
+                 uint16_t* adc, void* stream) {
+    if (n < 0 || bits < 1 || bits > 16 || !isfinite(gain) || !isfinite(baseline)) return LAR_EINVAL;
+    if (n == 0) return LAR_OK;
+    if (!wave || !adc) return LAR_EINVAL;
+    LAR_TRY(launch_digitize(wave, noise, n, gain, baseline, bits, adc, (hipStream_t)stream));
     return LAR_OK;
 }
 

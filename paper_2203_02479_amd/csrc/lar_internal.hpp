@@ -191,6 +191,39 @@ __device__ __forceinline__ void fft_lds(float2* A, const FftPlan& plan, int tid,
     }
 }
 
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit multiplies with the published multipliers and Weyl key
+// increments, counter (c0..c3) replaced by the output block.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// 52-bit uniform strictly inside (0, 1): ((a>>6) 2^26 + (b>>6) + 1/2) 2^-52.
+__device__ __forceinline__ double u52(uint32_t a, uint32_t b) {
+#pragma clang fp contract(off)
+    double hi = (double)(a >> 6), lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+
 // blockIdx -> tile with consecutive tiles on one XCD (workgroups are dealt
 // round-robin over the 8 XCDs, each with its own L2).
 __device__ __forceinline__ int xcd_tile(int b, int G) {
@@ -274,9 +307,32 @@ hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);
 // accumulate: dR += the gradient (else dR = the gradient).
-hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, float2* S, int64_t ldS, int n_wires,
-                               int n_imp, int nw_fft, int nt_fft, const float2* R, float2* dR,
-                               bool want_grid, float resp_scale, hipStream_t s, bool accumulate = true);
+// The grid-gradient spectrum goes to O (which may be S).
+hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, const float2* S, int64_t ldS, float2* O,
+                               int64_t ldO, int n_wires, int n_imp, int nw_fft, int nt_fft,
+                               const float2* R, float2* dR, bool want_grid, float resp_scale,
+                               hipStream_t s, bool accumulate = true);
+// Drift stage: parameters widened to double, plane projections
+// (cos, sin, offset) of up to kDriftMaxPlanes planes.
+constexpr int kDriftMaxPlanes = 8;
+constexpr int kDriftMaxBlocks = 2048;   // grid cap (and partial rows) of the drift kernels
+struct DriftConst {
+    double v, DL, DT, tau;
+    int n_planes;
+    double proj[kDriftMaxPlanes][3];
+};
+hipError_t launch_drift(const DriftConst& C, const float* q0, const float* t0, const float* xd,
+                        const float* y, const float* z, int64_t n, float* q, float* t, float* st,
+                        float* sx, float* x, hipStream_t s);
+// part: kDriftMaxBlocks * 4 doubles of scratch (used when dparams is given).
+hipError_t launch_drift_bwd(const DriftConst& C, const float* q0, const float* xd, int64_t n,
+                            const float* gq, const float* gt, const float* gst, const float* gsx,
+                            const float* gx, float* dq0, float* dt0, float* dxd, float* dy, float* dz,
+                            float* dparams, double* part, hipStream_t s);
+hipError_t launch_noise_spectrum(const float* amp, int F, int n_wires, uint64_t seed, uint32_t event,
+                                 uint32_t plane, float2* X, int64_t ld, hipStream_t s);
+hipError_t launch_digitize(const float* wave, const float* noise, int64_t n, float gain, float baseline,
+                           int bits, uint16_t* out, hipStream_t s);
 hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
                                 const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                                 hipStream_t s);

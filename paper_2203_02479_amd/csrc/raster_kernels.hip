@@ -11,8 +11,8 @@
 // larger than the per-depo weight slots, add their cells with direct global
 // atomics.
 //
-// Fluctuation (paper Sec. 3.1): per bin, Binomial(rint|q|, p) or
-// Poisson(|q| p) with p = wt*wx, uniforms from Philox4x32-10 (Salmon et al.,
+// Fluctuation (paper Sec. 3.1): per bin, Binomial(rint|q|, p), Poisson(|q| p)
+// or the normal approximation of the binomial, with p = wt*wx, uniforms from Philox4x32-10 (Salmon et al.,
 // SC'11) keyed by seed and counter (depo, event, bin, plane*2^24 + draw).
 // Binomial: inversion for n*min(p,1-p) < 10, BTRD otherwise (Hormann 1993);
 // Poisson: inversion for lambda < 10, PTRS otherwise (Hormann 1993).  The
@@ -41,34 +41,6 @@ struct PhiloxStream {
     uint32_t b0, b1, b2, b3;
     int left;   // 0: no buffered uniform, 2: second uniform of the block left, 3: primed block
 };
-
-__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
-                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        uint32_t n0 = hi1 ^ c1 ^ k0;
-        uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-    }
-}
-
-// 52-bit uniform strictly inside (0, 1): ((a>>6) 2^26 + (b>>6) + 1/2) 2^-52.
-__device__ __forceinline__ double u52(uint32_t a, uint32_t b) {
-#pragma clang fp contract(off)
-    double hi = (double)(a >> 6), lo = (double)(b >> 6);
-    return (hi * 67108864.0 + lo + 0.5) * (1.0 / 4503599627370496.0);
-}
 
 __device__ __forceinline__ void stream_init(PhiloxStream& s, uint64_t seed, uint32_t depo,
                                             uint32_t event, uint32_t bin, uint32_t plane) {
@@ -675,9 +647,41 @@ __device__ __forceinline__ float bin_count_in(int mode, float q, double p, uint6
     return q < 0.f ? -f : f;
 }
 
-// Signed count of one bin: sign(q) * Binomial(rint|q|, p) or Poisson(|q| p).
+// Signed count of one bin under the normal approximation of
+// Binomial(n = rint|q|, p) (mode 3; paper Sec. 3.1: the GPU port's choice):
+// mu = n p, sd = sqrt(mu (1 - p)), count = rint(mu + sd z) clipped to [0, n],
+// with z = sqrt(-2 log u1) cos(2 pi u2) (Box and Muller 1958) on the two
+// uniforms of the bin's first Philox block.  One block per bin, no branch
+// on the draw.
+__device__ __forceinline__ float bin_count_normal(float q, double p, uint64_t seed, uint32_t depo,
+                                                  uint32_t event, uint32_t bin, uint32_t plane) {
+#pragma clang fp contract(off)
+    const double n = rint(fabs((double)q));
+    double r;
+    if (!(n > 0.0) || !(p > 0.0)) {
+        r = 0.0;
+    } else if (p >= 1.0) {
+        r = n;
+    } else {
+        uint32_t c0 = depo, c1 = event, c2 = bin, c3 = plane << 24;
+        philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double u1 = u52(c0, c1), u2 = u52(c2, c3);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double z = rad * cos(6.283185307179586 * u2);
+        const double mu = n * p;
+        const double sd = sqrt(mu * (1.0 - p));
+        r = rint(mu + sd * z);
+        r = r < 0.0 ? 0.0 : (r > n ? n : r);
+    }
+    const float f = (float)r;
+    return q < 0.f ? -f : f;
+}
+
+// Signed count of one bin: sign(q) * Binomial(rint|q|, p) or Poisson(|q| p),
+// or the normal approximation of the binomial (mode 3).
 __device__ __forceinline__ float bin_count(int mode, float q, double p, uint64_t seed, uint32_t depo,
                                            uint32_t event, uint32_t bin, uint32_t plane) {
+    if (mode == 3) return bin_count_normal(q, p, seed, depo, event, bin, plane);
     return rejection_regime(mode, q, p)
                ? bin_count_in<true>(mode, q, p, seed, depo, event, bin, plane)
                : bin_count_in<false>(mode, q, p, seed, depo, event, bin, plane);
@@ -1063,6 +1067,36 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
                 }
                 // other lanes touch these cells for the next depo: keep program order
                 asm volatile("" ::: "memory");
+            }
+        } else if constexpr (MODE == 3) {
+            // ---- normal-approximation patches: every cell takes one Philox
+            // block and no data-dependent stage, so the cells are drawn 64 at
+            // a time in order (a batch mixes depos: LDS atomics on the tile)
+            const int total = __builtin_amdgcn_readfirstlane(s_off[wv][kSub]);
+            const uint64_t seed = A.seed;
+            const uint32_t event = A.event, plane = A.plane, nticks = (uint32_t)A.n_ticks;
+            const int64_t ld = A.ld;
+            int d = 0;
+            for (int c0 = 0; c0 < total; c0 += 64) {
+                const int c = c0 + lane;
+                if (c < total) {
+                    while (s_off[wv][d + 1] <= c) ++d;
+                    const int ant = abs(nt_[d]);
+                    const int local = c - s_off[wv][d];
+                    const int a = (int)(((float)local + 0.5f) * (1.0f / (float)ant));
+                    const int b = local - a * ant;
+                    const float* w = W + d * kSlot;
+                    const int j = jlo_[d] + b, m = mlo_[d] + a;
+                    const double p = (double)(w[b] * w[kMaxT + a]);
+                    const float v = bin_count_normal(q_[d], p, seed, (uint32_t)(base + d), event,
+                                                     (uint32_t)m * nticks + (uint32_t)j, plane);
+                    if (v != 0.f) {
+                        if (use_tile)
+                            atomicAdd(&tile[(m - mmin) * span_t + (j - jmin)], v);
+                        else
+                            grid_add(&grid[(int64_t)m * ld + j], v);
+                    }
+                }
             }
         } else {
             // ---- fluctuated patches.  Cells are classified 64 at a time by
@@ -1468,6 +1502,8 @@ __global__ __launch_bounds__(256) void k_raster_flagged(RasterItem one, const Ra
                     float v;
                     if (wide) {
                         v = bin_count(MODE, q, p, A.seed, (uint32_t)gd, A.event, bin, A.plane);
+                    } else if constexpr (MODE == 3) {
+                        continue;   // (mode 3 queues nothing: only wide depos are flagged)
                     } else {
                         // the bins k_raster queued: rejection bins the first stage
                         // left, inversion bins whose one-try search ran off its end
@@ -1682,8 +1718,14 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     hipLaunchKernelGGL(k_raster_flagged<M>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     if (mode == 1) {
         LAR_FLUCT(1)
-    } else {
+    } else if (mode == 2) {
         LAR_FLUCT(2)
+    } else {
+        // normal approximation: no queued draws, only depos wider than the
+        // weight slots are flagged
+        hipLaunchKernelGGL(k_raster<3>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, cap);
+        if (main_done) (void)hipEventRecord(main_done, s);
+        hipLaunchKernelGGL(k_raster_flagged<3>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     }
 #undef LAR_FLUCT
     return hipGetLastError();

@@ -40,6 +40,9 @@ SEED0 = 20220305
 
 SIN60 = math.sin(math.radians(60.0))
 COS60 = 0.5
+LIFETIME = 10000.0  # us, electron lifetime of the drift-stage inputs (10 ms)
+# pitch coordinate of each plane kind as (cos, sin, offset): x = z cos + y sin + offset
+PLANE_PROJ = {"U": (COS60, SIN60, 0.0), "V": (COS60, -SIN60, 3000.0 * SIN60), "W": (1.0, 0.0, 0.0)}
 
 
 def smooth_length(n: int, even: bool = False) -> int:
@@ -251,6 +254,26 @@ def cfg3_events(n_events=64, seed0=SEED0 + 300):
 
 def cfg4_events(n_events=16, n_depo=200_000, seed0=SEED0 + 400):
     return [cfg1_event(seed=seed0 + e, n_depo=n_depo, n_seg=24) for e in range(n_events)]
+
+
+def undrifted_groups(seed, n_seg, n_depo, n_points=0):
+    """Ionization groups before the drift stage, as float32 arrays
+    (q0, t0, xd, y, z): the tracks (and isolated points) of track_event, with
+    xd the distance to the anode along the drift and t0 = 0 (event time)."""
+    pts, q, _ = track_event(seed, n_seg, n_depo, None, n_points)
+    f = np.float32
+    return (q.astype(f), np.zeros(len(q), f), pts[:, 0].astype(f), pts[:, 1].astype(f),
+            pts[:, 2].astype(f))
+
+
+def noise_amplitude(plane, rms=200.0, rise=2.0, corner=0.02):
+    """Synthetic noise amplitude per frequency bin f <= nt_fft/2 (float32, in
+    waveform units): a flat floor that gives about `rms` per tick, times a
+    low-frequency rise 1 + rise * exp(-f / (corner * F))."""
+    F = plane.nt_fft // 2 + 1
+    f = np.arange(F, dtype=np.float64)
+    floor = rms * math.sqrt(plane.nt_fft / 2.0)
+    return (floor * (1.0 + rise * np.exp(-f / (corner * F)))).astype(np.float32)
 
 
 # --------------------------------------------------------------- responses

@@ -48,6 +48,15 @@ class lar_batch_item(ctypes.Structure):
                 ("wave_offset", ctypes.c_int64)]
 
 
+class lar_drift_params(ctypes.Structure):
+    _fields_ = [("speed", ctypes.c_float), ("diff_l", ctypes.c_float), ("diff_t", ctypes.c_float),
+                ("lifetime", ctypes.c_float)]
+
+
+class lar_plane_proj(ctypes.Structure):
+    _fields_ = [("cos_a", ctypes.c_float), ("sin_a", ctypes.c_float), ("offset", ctypes.c_float)]
+
+
 class lar_schedule(ctypes.Structure):
     _fields_ = [("row_threads", ctypes.c_int32), ("row_order", ctypes.c_int32), ("wire_cols", ctypes.c_int32),
                 ("wire_threads", ctypes.c_int32), ("wire_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -96,6 +105,16 @@ SIGNATURES = {
                                 ctypes.c_int),
     "lar_sample_counts": ([ctypes.c_int32, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.c_uint64,
                            _VP, _VP], ctypes.c_int),
+    "lar_drift": ([_P(lar_drift_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_int64, _P(lar_plane_proj),
+                   ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "lar_drift_backward_workspace": ([ctypes.c_int64, _P(_SZ)], ctypes.c_int),
+    "lar_drift_backward": ([_P(lar_drift_params), _VP, _VP, ctypes.c_int64, _P(lar_plane_proj), ctypes.c_int32]
+                           + [_VP] * 11 + [_VP, _SZ, _VP], ctypes.c_int),
+    "lar_noise_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
+    "lar_noise": ([_P(lar_plane), _VP, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _VP, _VP, _SZ, _VP],
+                  ctypes.c_int),
+    "lar_digitize": ([_VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP, _VP],
+                     ctypes.c_int),
 }
 
 _LIB = None
@@ -257,7 +276,7 @@ def spectrum_ld(plane) -> int:
 def fftconv_backward_spec(plane, grid_spec, resp, wave_grad, grid_grad, resp_grad, ws, accumulate=False,
                           stream=None):
     """grid_spec: a device buffer holding the grid spectrum (e.g. the fftconv
-    workspace after lar_fftconv); overwritten when grid_grad is given."""
+    workspace after lar_fftconv); only read."""
     pl = make_plane(plane)
     _check(_lib().lar_fftconv_backward_spec(ctypes.byref(pl), _ptr(grid_spec), _ptr(resp), _ptr(wave_grad),
                                             _ptr(grid_grad), _ptr(resp_grad), 1 if accumulate else 0, _ptr(ws),
@@ -290,6 +309,55 @@ def sample_counts(mode, q, p, ctr3, plane_id, seed, out, stream=None):
     n = q.numel()
     _check(_lib().lar_sample_counts(int(mode), n, _ptr(q), _ptr(p), _ptr(ctr3), int(plane_id), int(seed),
                                     _ptr(out), _stream(stream)), "lar_sample_counts")
+
+
+def _drift_args(params, proj):
+    v, dl, dt, tau = (float(a) for a in params)
+    pr = (lar_plane_proj * max(len(proj), 1))(*[lar_plane_proj(*(float(c) for c in row)) for row in proj])
+    return lar_drift_params(v, dl, dt, tau), pr, len(proj)
+
+
+def drift(params, q0, t0, xd, y, z, proj, q, t, sigma_t, sigma_x, x, stream=None):
+    """params = (speed, D_L, D_T, lifetime); proj = rows (cos, sin, offset)
+    per plane; x: [n_planes][n] device tensor (or None with no planes)."""
+    prm, pr, npl = _drift_args(params, proj)
+    _check(_lib().lar_drift(ctypes.byref(prm), _ptr(q0), _ptr(t0), _ptr(xd), _ptr(y), _ptr(z), q0.numel(), pr,
+                            npl, _ptr(q), _ptr(t), _ptr(sigma_t), _ptr(sigma_x), _ptr(x), _stream(stream)),
+           "lar_drift")
+
+
+def drift_backward_workspace(n) -> int:
+    nb = ctypes.c_size_t(0)
+    _check(_lib().lar_drift_backward_workspace(int(n), ctypes.byref(nb)), "lar_drift_backward_workspace")
+    return nb.value
+
+
+def drift_backward(params, q0, xd, proj, gq, gt, gsigma_t, gsigma_x, gx, dq0, dt0, dxd, dy, dz, dparams, ws,
+                   stream=None):
+    prm, pr, npl = _drift_args(params, proj)
+    wsp, wsn = (None, 0) if ws is None else (_ptr(ws), ws.numel())
+    _check(_lib().lar_drift_backward(ctypes.byref(prm), _ptr(q0), _ptr(xd), q0.numel(), pr, npl, _ptr(gq),
+                                     _ptr(gt), _ptr(gsigma_t), _ptr(gsigma_x), _ptr(gx), _ptr(dq0), _ptr(dt0),
+                                     _ptr(dxd), _ptr(dy), _ptr(dz), _ptr(dparams), wsp, wsn, _stream(stream)),
+           "lar_drift_backward")
+
+
+def noise_workspace(plane) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_noise_workspace(ctypes.byref(make_plane(plane)), ctypes.byref(n)), "lar_noise_workspace")
+    return n.value
+
+
+def noise(plane, amp, seed, event, plane_id, out, ws, stream=None):
+    pl = make_plane(plane)
+    _check(_lib().lar_noise(ctypes.byref(pl), _ptr(amp), int(seed), int(event), int(plane_id), _ptr(out), _ptr(ws),
+                            ws.numel(), _stream(stream)), "lar_noise")
+
+
+def digitize(wave, noise_, gain, baseline, bits, adc, stream=None):
+    """adc: uint16 codes (a torch.int16 / uint16 tensor of wave's size)."""
+    _check(_lib().lar_digitize(_ptr(wave), _ptr(noise_), wave.numel(), float(gain), float(baseline), int(bits),
+                               _ptr(adc), _stream(stream)), "lar_digitize")
 
 
 # ---------------------------------------------------------------- conveniences

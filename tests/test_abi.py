@@ -71,8 +71,17 @@ def test_host_side_argument_errors(lar):
     assert R(ctypes.byref(P), ctypes.byref(d), 3.0, None, None, None, 0, None) == lar.LAR_OK
     assert R(ctypes.byref(P), ctypes.byref(d), 0.0, None, None, None, 0, None) == lar.LAR_EINVAL
     assert R(None, ctypes.byref(d), 3.0, None, None, None, 0, None) == lar.LAR_EINVAL
-    f = lar.lar_fluct(3, 0, 0, 0, 0)
+    f = lar.lar_fluct(4, 0, 0, 0, 0)
     assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_EINVAL
+    f = lar.lar_fluct(3, 0, 0, 0, 0)
+    assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_OK
+    # a fluctuated grid of 2^32 cells or more would wrap the bin counter word
+    big = lar.make_plane(inputs.Plane(n_wires=1000, n_ticks=450000, n_imp=10, nt_fft=450000, nw_fft=1024))
+    for mode in (1, 2, 3):
+        f = lar.lar_fluct(mode, 0, 0, 0, 0)
+        assert R(ctypes.byref(big), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_ESIZE
+    f = lar.lar_fluct(0, 0, 0, 0, 0)
+    assert R(ctypes.byref(big), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_OK
     f = lar.lar_fluct(1, 0, 300, 0, 0)
     assert R(ctypes.byref(P), ctypes.byref(d), 3.0, ctypes.byref(f), None, None, 0, None) == lar.LAR_EINVAL
     one = ctypes.c_void_p(256)
@@ -85,7 +94,41 @@ def test_host_side_argument_errors(lar):
     assert L.lar_fftconv(ctypes.byref(P), one, one, one, None, 0, None) == lar.LAR_EWORKSPACE
     assert L.lar_fftconv(ctypes.byref(P), one, one, one, one, 16, None) == lar.LAR_EWORKSPACE
     assert L.lar_sample_counts(0, 1, one, one, one, 0, 0, one, None) == lar.LAR_EINVAL
+    assert L.lar_sample_counts(4, 1, one, one, one, 0, 0, one, None) == lar.LAR_EINVAL
     assert L.lar_sample_counts(1, 0, None, None, None, 0, 0, None, None) == lar.LAR_OK
+
+
+def test_stage_calls_host_side_errors(lar):
+    L = lar.lib()
+    one = ctypes.c_void_p(256)
+    prm = lar.lar_drift_params(1.6, 4e-4, 8.8e-4, 1e4)
+    proj = (lar.lar_plane_proj * 9)()
+    D = L.lar_drift
+    assert D(ctypes.byref(prm), None, None, None, None, None, 0, proj, 3, None, None, None, None, None,
+             None) == lar.LAR_OK
+    assert D(ctypes.byref(prm), one, one, one, one, one, 5, proj, 9, one, one, one, one, one, None) == lar.LAR_EINVAL
+    assert D(ctypes.byref(prm), one, one, one, one, one, 5, proj, 2, one, one, one, one, None,
+             None) == lar.LAR_EINVAL
+    assert D(ctypes.byref(prm), one, one, one, one, one, -1, proj, 0, one, one, one, one, None,
+             None) == lar.LAR_EINVAL
+    for bad in ((0.0, 4e-4, 8.8e-4, 0.0), (1.6, -1.0, 8.8e-4, 0.0), (1.6, 4e-4, float("nan"), 0.0)):
+        b = lar.lar_drift_params(*bad)
+        assert D(ctypes.byref(b), one, one, one, one, one, 5, proj, 0, one, one, one, one, None,
+                 None) == lar.LAR_EINVAL
+    assert lar.drift_backward_workspace(10) == 2048 * 4 * 8
+    B = L.lar_drift_backward
+    args = [one] * 11
+    assert B(ctypes.byref(prm), one, one, 5, proj, 1, *args, None, 0, None) == lar.LAR_EWORKSPACE
+    Z = L.lar_digitize
+    assert Z(one, None, 5, 1.0, 0.0, 17, one, None) == lar.LAR_EINVAL
+    assert Z(one, None, 5, 1.0, 0.0, 0, one, None) == lar.LAR_EINVAL
+    assert Z(one, None, 5, float("inf"), 0.0, 12, one, None) == lar.LAR_EINVAL
+    assert Z(None, None, 0, 1.0, 0.0, 12, None, None) == lar.LAR_OK
+    P = inputs.cfg1_plane()
+    assert lar.noise_workspace(P) == (480 * ((3073 + 15) // 16 * 16) * 8 + 255) // 256 * 256
+    pl = lar.make_plane(P)
+    assert L.lar_noise(ctypes.byref(pl), one, 0, 0, 300, one, one, 1 << 30, None) == lar.LAR_EINVAL
+    assert L.lar_noise(ctypes.byref(pl), one, 0, 0, 1, one, one, 256, None) == lar.LAR_EWORKSPACE
 
 
 def test_schedule_registry_host_side(lar):

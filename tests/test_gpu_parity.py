@@ -198,7 +198,7 @@ def _injected(n, seed=5):
     return q, p, ctr
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_sampler_bit_exact(mode):
     torch, lar = _torch(), _lar()
     q, p, ctr = _injected(200_000, seed=mode)
@@ -212,10 +212,12 @@ def test_sampler_bit_exact(mode):
     assert len(mism) == 0, (len(mism), q[mism[:5]], p[mism[:5]], got[mism[:5]], ref[mism[:5]])
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_raster_fluct_cfg0_matches_oracle_keys(mode):
     """Same keys, p equal up to FP32 rounding: nearly every bin is identical,
-    and the totals agree with the mean path within the statistical spread."""
+    and the totals agree with the mean path within the statistical spread
+    (binomial, Poisson; the rounded, clipped normal approximation is biased
+    at small means, so its total is compared with the oracle's)."""
     ev = inputs.cfg0_event()
     P, dep = ev.planes[0], ev.depos[0]
     seed = inputs.SEED0
@@ -224,6 +226,9 @@ def test_raster_fluct_cfg0_matches_oracle_keys(mode):
     assert np.array_equal(g, np.round(g))
     same = np.mean(g == ref)
     assert same > 0.9999, same
+    if mode == 3:
+        assert abs(g.sum() - ref.sum()) < 1e-4 * abs(ref.sum())
+        return
     mean = oracle.raster_mean(P, dep)
     # independent bins: Var(sum) = sum N p (1 - p) <= sum N p (binomial), = sum |q| p (Poisson)
     z = (g.sum() - mean.sum()) / math.sqrt(mean.sum())
@@ -278,7 +283,7 @@ def test_fluct_queue_capacity_does_not_change_counts(mode):
         gpu_raster(P, dep, fluct=fl, ws_bytes=fixed - 256)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_fluct_wide_depos_with_queue_overflow(mode):
     """Depos wider than the hot raster kernel's weight slots (16 ticks, 32
     impact rows), mixed with regular ones in the same sub-chunks: the oracle's
@@ -312,7 +317,7 @@ def test_fluct_point_charges_large_q():
     assert g.sum() == pytest.approx(ref.sum(), rel=1e-3)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_raster_fluct_cfg1_full_size(mode):
     """The headline event (500k depos, 480 x 10 rows x 6000 ticks) in the
     launch configuration the benchmark times: integer counts summed in
