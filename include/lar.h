@@ -133,6 +133,23 @@ int lar_fftconv_workspace(const lar_plane *plane, size_t *bytes);
 int lar_fftconv(const lar_plane *plane, const float *grid, const float *resp, float *wave,
                 void *workspace, size_t ws_bytes, void *stream);
 
+/* lar_fftconv for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result as lar_fftconv, with the spectra held in a
+ * fixed device array of lar_fftconv_noalloc_max_bytes() bytes (256 MiB,
+ * one per GPU the library runs on, kept until the process ends) instead of
+ * a workspace.  A plane whose lar_fftconv workspace exceeds that size gets
+ * LAR_ESIZE (n_wires * n_imp + n_wires rows of (nt_fft/2 + 1, rounded up to
+ * 16) complex64 must fit: e.g. 8000 + 800 rows at nt_fft = 6144).  Nothing
+ * is allocated; the array's address is looked up on the first call on each
+ * device.  Every call on one GPU shares the array: calls that overlap on
+ * one GPU (several streams or threads) race and must be serialised by the
+ * caller.  The array holds the last call's spectra; nothing in it needs to
+ * start at zero. */
+size_t lar_fftconv_noalloc_max_bytes(void);
+int lar_fftconv_noalloc(const lar_plane *plane, const float *grid, const float *resp, float *wave,
+                        void *stream);
+
 /* One plane end to end: clear an internal grid, lar_raster, lar_fftconv.
  * The workspace covers the grid, the raster's queue for n_depos depos and
  * the convolution's buffers. */

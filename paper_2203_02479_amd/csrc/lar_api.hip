@@ -4,6 +4,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "lar_internal.hpp"
 
 using namespace lar;
@@ -213,6 +215,47 @@ int lar_fftconv(const lar_plane* plane, const float* grid, const float* resp, fl
     if (!grid || !resp || !wave) return LAR_EINVAL;
     if (!ws || ws_bytes < fftconv_bytes(plane)) return LAR_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    return fftconv_impl(plane, grid, resp, wave, ws, (hipStream_t)stream);
+}
+
+// ---- the convolution without a caller workspace, for callers that cannot
+// allocate: its time and wire-pass spectra live in one file-scope device
+// array.  In host code `scratch` names a host-side stand-in, so its device
+// address is looked up once per device (with that device current) and only
+// that address is ever handed to kernels.
+static constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_on_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return LAR_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (!ptr) return LAR_EINVAL;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LAR_OK;
+}
+
+size_t lar_fftconv_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int lar_fftconv_noalloc(const lar_plane* plane, const float* grid, const float* resp, float* wave,
+                        void* stream) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if (!grid || !resp || !wave) return LAR_EINVAL;
+    if (fftconv_bytes(plane) > kScratchBytes) return LAR_ESIZE;
+    void* ws = nullptr;
+    if ((st = scratch_on_current_device(&ws))) return st;
     return fftconv_impl(plane, grid, resp, wave, ws, (hipStream_t)stream);
 }
 

@@ -77,6 +77,8 @@ SIGNATURES = {
                    ctypes.c_int),
     "lar_fftconv_workspace": ([_P(lar_plane), _P(_SZ)], ctypes.c_int),
     "lar_fftconv": ([_P(lar_plane), _VP, _VP, _VP, _VP, _SZ, _VP], ctypes.c_int),
+    "lar_fftconv_noalloc_max_bytes": ([], ctypes.c_size_t),
+    "lar_fftconv_noalloc": ([_P(lar_plane), _VP, _VP, _VP, _VP], ctypes.c_int),
     "lar_sim_plane_workspace": ([_P(lar_plane), ctypes.c_int64, _P(lar_fluct), _P(_SZ)], ctypes.c_int),
     "lar_sim_plane": ([_P(lar_plane), _P(lar_depos), ctypes.c_float, _P(lar_fluct), _VP, _VP, _VP, _SZ,
                        _VP], ctypes.c_int),
@@ -230,6 +232,17 @@ def fftconv(plane, grid, resp, wave, ws, stream=None):
     pl = make_plane(plane)
     _check(_lib().lar_fftconv(ctypes.byref(pl), _ptr(grid), _ptr(resp), _ptr(wave), _ptr(ws), ws.numel(),
                               _stream(stream)), "lar_fftconv")
+
+
+def fftconv_noalloc(plane, grid, resp, wave, stream=None):
+    """lar_fftconv without a workspace (the library's fixed device array)."""
+    pl = make_plane(plane)
+    _check(_lib().lar_fftconv_noalloc(ctypes.byref(pl), _ptr(grid), _ptr(resp), _ptr(wave), _stream(stream)),
+           "lar_fftconv_noalloc")
+
+
+def fftconv_noalloc_max_bytes() -> int:
+    return int(_lib().lar_fftconv_noalloc_max_bytes())
 
 
 def sim_plane_workspace(plane, n_depos=0, fluct=None) -> int:
