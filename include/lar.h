@@ -292,13 +292,16 @@ int lar_digitize(const float *wave, const float *noise, int64_t n, float gain, f
                  int32_t bits, uint16_t *adc, void *stream);
 
 /* ---------------------------------------------------------------- batching
- * Many (event, plane) items in one launch sequence (no paper counterpart:
- * the paper raises throughput by running independent processes per GPU,
- * Sec. 3.3).  One persistent raster launch covers every item's depos; each
- * plane type then takes one launch per FFT stage for all of its items, with
- * the response spectrum shared.  Each item's waveforms equal those of
- * lar_sim_plane on the same depos with fluct {mode, event, plane, seed}
- * (fluctuated counts exactly; mean grids up to float summation order). */
+ * Many (event, plane) items in few launches (no paper counterpart: the
+ * paper raises throughput by running independent processes per GPU,
+ * Sec. 3.3).  Items are grouped by plane type; each type's items run in
+ * waves of at most K items, K the largest that the given workspace holds:
+ * per wave one raster launch over the wave's items (their table is built on
+ * the device by a prefix sum of their depo sub-chunks) and one launch per
+ * FFT stage, the response spectrum of the type shared by the wave's items.
+ * Each item's waveforms equal those of lar_sim_plane on the same depos with
+ * fluct {mode, event, plane, seed} (fluctuated counts exactly; mean grids up
+ * to float summation order). */
 typedef struct lar_batch_item {
     int32_t plane_type;     /* index into planes[] and resp[] */
     uint32_t event;         /* fluctuation counter words of this item */
@@ -311,25 +314,53 @@ typedef struct lar_batch_item {
 
 typedef struct lar_batch lar_batch;    /* opaque plan */
 
-/* Workspace for a plan: item and row tables, every item's grid, time
- * spectra and wire-pass output, and the raster queue (fluct only).
+/* Workspace for waves of at most max_wave items per plane type (0: every
+ * item of a type in one wave, the most the plan can use): item tables,
+ * one wave's grids, time spectra and wire-pass outputs (an arena shared by
+ * every wave), and the raster queue of the largest wave (fluct only).
+ * lar_batch_workspace(...) = lar_batch_workspace_waves(..., 0, ...).
  * n_items < 2^27 (LAR_ESIZE otherwise). */
+int lar_batch_workspace_waves(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
+                              int32_t n_items, const lar_fluct *fluct, int32_t max_wave,
+                              size_t *bytes);
 int lar_batch_workspace(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
                         int32_t n_items, const lar_fluct *fluct, size_t *bytes);
 
 /* Build a plan for these exact device buffers: depos holds all items'
  * depos (concatenated), resp[t] the spectrum of plane type t, wave the
- * output.  Uploads the tables to the workspace (a synchronous copy) and,
- * with use_graph, captures the whole sequence into a hipGraph.  The
- * contents of depos / resp may change between runs; their addresses and
- * the item counts may not.  Setup call: it allocates host memory and the
- * graph. */
+ * output.  The waves are as large as ws_bytes allows (LAR_EWORKSPACE when
+ * not even one item per wave fits).  Uploads the tables to the workspace (a
+ * synchronous copy) and, with use_graph, captures the whole sequence into a
+ * hipGraph.  The contents of depos / resp may change between runs; their
+ * addresses and the item counts may not.  Setup call: it allocates host
+ * memory and the graph. */
 int lar_batch_create(const lar_plane *planes, int32_t n_types, const float *const *resp,
                      const lar_depos *depos, float nsigma, const lar_fluct *fluct,
                      const lar_batch_item *items, int32_t n_items, float *wave, void *workspace,
                      size_t ws_bytes, int32_t use_graph, lar_batch **plan);
+/* The plan's wave count and largest wave (either pointer may be NULL). */
+int lar_batch_waves(const lar_batch *plan, int32_t *n_waves, int32_t *max_items);
 /* Run the plan on `stream` (one graph launch with use_graph). */
 int lar_batch_run(lar_batch *plan, void *stream);
+
+/* Backward of a mean-path plan (fluct NULL or mode 0; LAR_EINVAL
+ * otherwise), the batched form of lar_fftconv_backward + lar_raster_backward
+ * (no paper counterpart): for L with dL/dwave = wave_grad (the layout of
+ * wave), per wave of items: the grids and their time spectra are
+ * recomputed (patches are not stored), the waveform gradients transformed,
+ * the adjoint wire pass runs over the wave's items with the response
+ * gradient of each tile summed over the items in registers, then the grid
+ * gradients and the depo gradients.
+ *   resp_grad[t] ([n_imp][nw_fft][nt_fft/2+1] complex, as resp) =
+ *       the sum over the items of type t of their response gradients,
+ *       OVERWRITTEN (types without items untouched); resp_grad or any
+ *       entry may be NULL;
+ *   dq, dt, dx, dsigma_t, dsigma_x: the layout of the depo arrays, each
+ *       item's depos OVERWRITTEN with their gradients; all five or none.
+ * Uses the plan's workspace (do not overlap with lar_batch_run); eager
+ * launches on `stream`. */
+int lar_batch_backward(lar_batch *plan, const float *wave_grad, float *const *resp_grad, float *dq,
+                       float *dt, float *dx, float *dsigma_t, float *dsigma_x, void *stream);
 int lar_batch_destroy(lar_batch *plan);
 
 /* ---------------------------------------------------------------- schedules

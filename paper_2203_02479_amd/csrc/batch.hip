@@ -1,15 +1,27 @@
 // batch.hip -- many (event, plane) items in one launch sequence, captured
-// once into a hipGraph and replayed.
+// once into a hipGraph and replayed (the paper raises throughput by running
+// independent processes per GPU, Sec. 3.3; here one process runs them as
+// batched launches sharing each plane type's response).
 //
-// Layout in the caller's workspace (all 256-byte aligned):
-//   item table (RasterItem[n_items]) | output row-offset table (int64 per
-//   waveform row) | grids, grouped by plane type | time spectra, grouped by
-//   plane type | wire-pass outputs, grouped by plane type | raster queue.
-// Grouping by plane type makes the rows of one type contiguous, so each
-// type's three FFT stages are one launch each, whatever the item order.
+// Items are grouped by plane type and each type's items are cut into waves
+// of at most K items, K as large as the caller's workspace allows.  One wave
+// holds K grids, K time spectra and K wire-pass outputs in an arena that
+// every wave of every type reuses, so memory is bounded by K, not by the
+// number of items.  Per wave: clear the grids, one raster launch over the
+// wave's items (a table of them, built on the device each run by a
+// segmented prefix sum of their sub-chunk counts), one launch per FFT stage
+// over the wave's rows; the wire pass runs the blocks of one tile for every
+// item of the wave together on one XCD, so the tile's response slabs come
+// from that XCD's L2.
+//
+// Workspace layout (all 256-byte aligned):
+//   item records in wave order | raster item table | wave-local sub-chunk
+//   prefix | per-type plane constants | output row offsets | arena | raster
+//   queue
 #include <limits.h>
 #include <math.h>
 
+#include <algorithm>
 #include <functional>
 #include <new>
 #include <vector>
@@ -17,12 +29,6 @@
 #include "lar_internal.hpp"
 
 using namespace lar;
-
-struct lar_batch {
-    std::vector<std::function<hipError_t(hipStream_t)>> steps;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
 
 namespace {
 
@@ -46,19 +52,49 @@ bool plane_ok(const lar_plane& p) {
     return true;
 }
 
-struct Layout {
-    size_t table, rowoff, grids, specs, mouts, raster, total;
-    std::vector<size_t> grid_at, spec_at, mout_at;   // per item
-    std::vector<size_t> type_grid, type_spec, type_mout;
-    std::vector<int> type_count;
-    int64_t total_sub = 0, total_rows_out = 0;
+// Per-item record on the device (wave order).
+struct DevItem {
+    int32_t type, slot;         // plane type, position within its wave
+    uint32_t event, plane;
+    int64_t depo_offset, n_depos;
+    int32_t wave_first;         // index (wave order) of the first item of its wave
+    int32_t pad;
 };
 
-int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
-           const lar_fluct* fluct, Layout& L) {
+// Per-type constants the table kernel needs.
+struct DevType {
+    RasterArgs proto;           // geometry and fluctuation; event and plane set per item
+    int64_t grid_stride;        // floats between the grids of consecutive slots
+    float* grid0;               // grid of slot 0 in the arena
+};
+
+struct Wave {
+    int type, first, count;     // items [first, first + count) in wave order
+    int64_t n_depos, total_sub;
+};
+
+struct Layout {
+    size_t items, table, prefix, types, rowoff, arena, raster, total;
+    int K = 0;                                  // items per wave
+    std::vector<int> order;                     // wave order -> item index
+    std::vector<Wave> waves;
+    std::vector<size_t> gsz, ssz, msz;          // per type, per slot
+    size_t arena_bytes = 0, raster_bytes = 0;
+    int64_t total_rows_out = 0;
+};
+
+size_t raster_ws_for(const lar_fluct* f, int64_t sub, int64_t depos) {
+    if (!f || f->mode == 0 || sub <= 0) return 0;
+    size_t b = raster_ws_fixed_subs(sub);
+    if (f->mode != 3) b += al(((size_t)depos * 48 + 4096) * kDeferredBytes);
+    return b;
+}
+
+int check_items(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
+                const lar_fluct* fluct) {
     if (!planes || n_types < 1 || !items || n_items < 1) return LAR_EINVAL;
     if (n_items >= (1 << 27)) return LAR_ESIZE;   // item index shares a 32-bit word with queue marks
-    if (fluct && (fluct->mode < 0 || fluct->mode > 3)) return LAR_EINVAL;
+    if (fluct && (fluct->mode < 0 || fluct->mode > 3 || fluct->plane >= 256u)) return LAR_EINVAL;
     for (int t = 0; t < n_types; ++t) {
         if (!plane_ok(planes[t])) return LAR_ESIZE;
         // a drawn bin's counter word is m * n_ticks + j
@@ -66,70 +102,205 @@ int layout(const lar_plane* planes, int n_types, const lar_batch_item* items, in
             (int64_t)planes[t].n_wires * planes[t].n_imp * planes[t].n_ticks > (int64_t)UINT32_MAX)
             return LAR_ESIZE;
     }
-    L.type_count.assign(n_types, 0);
-    int64_t total_depos = 0;
     for (int i = 0; i < n_items; ++i) {
         const lar_batch_item& it = items[i];
         if (it.plane_type < 0 || it.plane_type >= n_types || it.n_depos < 0 || it.depo_offset < 0 ||
             it.wave_offset < 0 || it.plane >= 256u)
             return LAR_EINVAL;
         if (it.n_depos > (int64_t)UINT32_MAX) return LAR_ESIZE;
-        L.type_count[it.plane_type]++;
-        L.total_sub += raster_subchunks(it.n_depos);
-        L.total_rows_out += planes[it.plane_type].n_wires;
-        total_depos += it.n_depos;
     }
-    size_t off = 0;
-    L.table = off;  off += al(sizeof(RasterItem) * (size_t)n_items);
-    L.rowoff = off; off += al(sizeof(int64_t) * (size_t)L.total_rows_out);
-    // per type blocks, items of a type in item order
-    L.type_grid.assign(n_types, 0);
-    L.type_spec.assign(n_types, 0);
-    L.type_mout.assign(n_types, 0);
-    std::vector<size_t> gsz(n_types), ssz(n_types), msz(n_types);
+    return LAR_OK;
+}
+
+// Layout for waves of at most K items per type (K >= 1).
+void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
+            const lar_fluct* fluct, int K, Layout& L) {
+    L.K = K;
+    L.order.clear();
+    L.waves.clear();
+    L.gsz.assign(n_types, 0);
+    L.ssz.assign(n_types, 0);
+    L.msz.assign(n_types, 0);
+    L.arena_bytes = 0;
+    L.raster_bytes = 0;
+    L.total_rows_out = 0;
+    int64_t max_sub = 0, max_depos = 0;
     for (int t = 0; t < n_types; ++t) {
         const lar_plane& p = planes[t];
-        gsz[t] = al((size_t)p.n_wires * p.n_imp * p.n_ticks * sizeof(float));
-        ssz[t] = al((size_t)p.n_wires * p.n_imp * spec_ld_of(p) * sizeof(float2));
-        msz[t] = al((size_t)p.n_wires * spec_ld_of(p) * sizeof(float2));
+        L.gsz[t] = al((size_t)p.n_wires * p.n_imp * p.n_ticks * sizeof(float));
+        L.ssz[t] = al((size_t)p.n_wires * p.n_imp * spec_ld_of(p) * sizeof(float2));
+        L.msz[t] = al((size_t)p.n_wires * spec_ld_of(p) * sizeof(float2));
+        std::vector<int> mine;
+        for (int i = 0; i < n_items; ++i)
+            if (items[i].plane_type == t) mine.push_back(i);
+        for (size_t a = 0; a < mine.size(); a += (size_t)K) {
+            Wave w;
+            w.type = t;
+            w.first = (int)L.order.size();
+            w.count = (int)std::min<size_t>((size_t)K, mine.size() - a);
+            w.n_depos = 0;
+            w.total_sub = 0;
+            for (int j = 0; j < w.count; ++j) {
+                const lar_batch_item& it = items[mine[a + j]];
+                L.order.push_back(mine[a + j]);
+                w.n_depos += it.n_depos;
+                w.total_sub += raster_subchunks(it.n_depos);
+                L.total_rows_out += p.n_wires;
+            }
+            max_sub = std::max(max_sub, w.total_sub);
+            max_depos = std::max(max_depos, w.n_depos);
+            L.arena_bytes = std::max(L.arena_bytes, (L.gsz[t] + L.ssz[t] + L.msz[t]) * (size_t)w.count);
+            L.waves.push_back(w);
+        }
     }
-    L.grids = off;
-    for (int t = 0; t < n_types; ++t) { L.type_grid[t] = off; off += gsz[t] * L.type_count[t]; }
-    L.specs = off;
-    for (int t = 0; t < n_types; ++t) { L.type_spec[t] = off; off += ssz[t] * L.type_count[t]; }
-    L.mouts = off;
-    for (int t = 0; t < n_types; ++t) { L.type_mout[t] = off; off += msz[t] * L.type_count[t]; }
-    L.grid_at.resize(n_items);
-    L.spec_at.resize(n_items);
-    L.mout_at.resize(n_items);
-    std::vector<int> rank(n_types, 0);
-    for (int i = 0; i < n_items; ++i) {
-        const int t = items[i].plane_type;
-        L.grid_at[i] = L.type_grid[t] + gsz[t] * rank[t];
-        L.spec_at[i] = L.type_spec[t] + ssz[t] * rank[t];
-        L.mout_at[i] = L.type_mout[t] + msz[t] * rank[t];
-        rank[t]++;
-    }
-    L.raster = off;
-    if (fluct && fluct->mode != 0)
-        off += raster_ws_fixed_subs(L.total_sub) +
-               (fluct->mode == 3 ? 0 : al(((size_t)total_depos * 48 + 4096) * kDeferredBytes));
+    L.raster_bytes = raster_ws_for(fluct, max_sub, max_depos);
+    size_t off = 0;
+    L.items = off;  off += al(sizeof(DevItem) * (size_t)n_items);
+    L.table = off;  off += al(sizeof(RasterItem) * (size_t)n_items);
+    L.prefix = off; off += al(sizeof(int64_t) * (size_t)n_items);
+    L.types = off;  off += al(sizeof(DevType) * (size_t)n_types);
+    L.rowoff = off; off += al(sizeof(int64_t) * (size_t)L.total_rows_out);
+    L.arena = off;  off += L.arena_bytes;
+    L.raster = off; off += L.raster_bytes;
     L.total = off;
-    return LAR_OK;
+}
+
+int max_type_count(const lar_batch_item* items, int n_items, int n_types) {
+    std::vector<int> c(n_types, 0);
+    int m = 0;
+    for (int i = 0; i < n_items; ++i) m = std::max(m, ++c[items[i].plane_type]);
+    return m;
+}
+
+// ---- device table of the raster items: one workgroup, a prefix sum of the
+// items' sub-chunk counts in wave order, restarted at each wave
+constexpr int kTableThreads = 1024;
+
+__global__ __launch_bounds__(kTableThreads) void k_batch_table(const DevItem* __restrict__ it,
+                                                                const DevType* __restrict__ ty, int n_items,
+                                                                lar_depos depos, RasterItem* __restrict__ out,
+                                                                int64_t* __restrict__ prefix) {
+    __shared__ int64_t s_scan[kTableThreads];
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    // global exclusive prefix of the sub-chunk counts
+    for (int c0 = 0; c0 < n_items; c0 += kTableThreads) {
+        const int i = c0 + (int)threadIdx.x;
+        const int64_t v = i < n_items ? raster_subchunks(it[i].n_depos) : 0;
+        s_scan[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kTableThreads; o <<= 1) {   // Hillis-Steele inclusive scan
+            const int64_t a = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_scan[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < n_items) prefix[i] = s_carry + s_scan[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kTableThreads - 1) s_carry += s_scan[kTableThreads - 1];
+        __syncthreads();
+    }
+    // every prefix is written; each item's wave-local start, and its record
+    for (int i = threadIdx.x; i < n_items; i += kTableThreads) {
+        const DevItem d = it[i];
+        const DevType& T = ty[d.type];
+        RasterItem r;
+        r.A = T.proto;
+        r.A.event = d.event;
+        r.A.plane = d.plane;
+        r.q = depos.q + d.depo_offset;
+        r.t = depos.t + d.depo_offset;
+        r.x = depos.x + d.depo_offset;
+        r.st = depos.sigma_t + d.depo_offset;
+        r.sx = depos.sigma_x + d.depo_offset;
+        r.grid = T.grid0 + (int64_t)d.slot * T.grid_stride;
+        r.n = d.n_depos;
+        r.sub_begin = prefix[i] - prefix[d.wave_first];
+        out[i] = r;
+    }
+}
+
+}  // namespace
+
+struct lar_batch {
+    std::vector<std::function<hipError_t(hipStream_t)>> steps;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // for the backward pass (mean path only)
+    int mode = 0;
+    std::vector<lar_plane> planes;
+    std::vector<const float*> resp;
+    std::vector<lar_batch_item> items;   // wave order
+    std::vector<Wave> waves;
+    std::vector<RasterArgs> proto;       // per type
+    lar_depos depos{};
+    char* arena = nullptr;
+    const RasterItem* dtab = nullptr;
+    const int64_t* drow = nullptr;
+    const DevItem* ditp = nullptr;
+    const DevType* dtyp = nullptr;
+    int64_t* dpre = nullptr;
+    bool rows_even = false;
+    std::vector<int64_t> row0;           // per wave: first output row in drow
+    std::vector<size_t> gsz, ssz, msz;
+};
+
+namespace {
+
+RasterArgs args_of(const lar_plane& p, float nsigma, const lar_fluct* fluct) {
+    RasterArgs a;
+    a.n_ticks = p.n_ticks;
+    a.n_rows = p.n_wires * p.n_imp;
+    a.ld = p.n_ticks;
+    a.org_t = (double)p.t0;
+    a.wd_t = (double)p.tick;
+    a.org_x = (double)p.x0 - (double)p.pitch / 2.0;
+    a.wd_x = (double)p.pitch / (double)p.n_imp;
+    a.nsig = (double)nsigma;
+    a.mode = fluct ? fluct->mode : 0;
+    a.event = a.plane = 0u;
+    a.seed = fluct ? fluct->seed : 0ull;
+    return a;
+}
+
+// Largest wave size whose layout fits in ws_bytes (0 if none does).
+int fit_waves(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
+              const lar_fluct* fluct, size_t ws_bytes, Layout& L) {
+    int lo = 1, hi = max_type_count(items, n_items, n_types), best = 0;
+    while (lo <= hi) {
+        const int mid = lo + (hi - lo) / 2;
+        layout(planes, n_types, items, n_items, fluct, mid, L);
+        if (L.total <= ws_bytes) {
+            best = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (best) layout(planes, n_types, items, n_items, fluct, best, L);
+    return best;
 }
 
 }  // namespace
 
 extern "C" {
 
-int lar_batch_workspace(const lar_plane* planes, int32_t n_types, const lar_batch_item* items,
-                        int32_t n_items, const lar_fluct* fluct, size_t* bytes) {
-    if (!bytes) return LAR_EINVAL;
-    Layout L;
-    int st = layout(planes, n_types, items, n_items, fluct, L);
+int lar_batch_workspace_waves(const lar_plane* planes, int32_t n_types, const lar_batch_item* items,
+                              int32_t n_items, const lar_fluct* fluct, int32_t max_wave, size_t* bytes) {
+    if (!bytes || max_wave < 0) return LAR_EINVAL;
+    int st = check_items(planes, n_types, items, n_items, fluct);
     if (st) return st;
+    const int m = max_type_count(items, n_items, n_types);
+    Layout L;
+    layout(planes, n_types, items, n_items, fluct, max_wave == 0 ? m : std::min(max_wave, m), L);
     *bytes = L.total;
     return LAR_OK;
+}
+
+int lar_batch_workspace(const lar_plane* planes, int32_t n_types, const lar_batch_item* items,
+                        int32_t n_items, const lar_fluct* fluct, size_t* bytes) {
+    return lar_batch_workspace_waves(planes, n_types, items, n_items, fluct, 0, bytes);
 }
 
 int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* const* resp,
@@ -138,142 +309,150 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
                      size_t ws_bytes, int32_t use_graph, lar_batch** out) {
     if (!out || !resp || !depos || !wave || !(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
     *out = nullptr;
-    Layout L;
-    int st = layout(planes, n_types, items, n_items, fluct, L);
+    int st = check_items(planes, n_types, items, n_items, fluct);
     if (st) return st;
+    std::vector<int> count(n_types, 0);
+    for (int i = 0; i < n_items; ++i) count[items[i].plane_type]++;
     for (int t = 0; t < n_types; ++t)
-        if (L.type_count[t] && !resp[t]) return LAR_EINVAL;
+        if (count[t] && !resp[t]) return LAR_EINVAL;
     int64_t total_depos = 0;
     for (int i = 0; i < n_items; ++i)
-        total_depos = items[i].depo_offset + items[i].n_depos > total_depos
-                          ? items[i].depo_offset + items[i].n_depos
-                          : total_depos;
+        total_depos = std::max(total_depos, items[i].depo_offset + items[i].n_depos);
     if (total_depos > depos->n) return LAR_EINVAL;
     if (depos->n > 0 && (!depos->q || !depos->t || !depos->x || !depos->sigma_t || !depos->sigma_x))
         return LAR_EINVAL;
-    if (!ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    Layout L;
+    if (!fit_waves(planes, n_types, items, n_items, fluct, ws_bytes, L)) return LAR_EWORKSPACE;
     char* W = reinterpret_cast<char*>(ws);
     const int mode = fluct ? fluct->mode : 0;
 
-    // ---- tables (host), uploaded once
-    std::vector<RasterItem> tab(n_items);
+    // ---- host tables, uploaded once
+    std::vector<DevItem> dit(n_items);
+    std::vector<DevType> dty(n_types);
+    for (int t = 0; t < n_types; ++t) {
+        dty[t].proto = args_of(planes[t], nsigma, fluct);
+        dty[t].grid_stride = (int64_t)(L.gsz[t] / sizeof(float));
+        dty[t].grid0 = reinterpret_cast<float*>(W + L.arena);
+    }
     std::vector<int64_t> rowoff;
     rowoff.reserve(L.total_rows_out);
+    std::vector<int64_t> row0;
     bool even = true;
-    int64_t sub = 0;
-    for (int i = 0; i < n_items; ++i) {
-        const lar_batch_item& it = items[i];
-        const lar_plane& p = planes[it.plane_type];
-        RasterItem& r = tab[i];
-        r.A.n_ticks = p.n_ticks;
-        r.A.n_rows = p.n_wires * p.n_imp;
-        r.A.ld = p.n_ticks;
-        r.A.org_t = (double)p.t0;
-        r.A.wd_t = (double)p.tick;
-        r.A.org_x = (double)p.x0 - (double)p.pitch / 2.0;
-        r.A.wd_x = (double)p.pitch / (double)p.n_imp;
-        r.A.nsig = (double)nsigma;
-        r.A.mode = mode;
-        r.A.event = it.event;
-        r.A.plane = it.plane;
-        r.A.seed = fluct ? fluct->seed : 0ull;
-        r.q = depos->q + it.depo_offset;
-        r.t = depos->t + it.depo_offset;
-        r.x = depos->x + it.depo_offset;
-        r.st = depos->sigma_t + it.depo_offset;
-        r.sx = depos->sigma_x + it.depo_offset;
-        r.grid = reinterpret_cast<float*>(W + L.grid_at[i]);
-        r.n = it.n_depos;
-        r.sub_begin = sub;
-        sub += raster_subchunks(it.n_depos);
-    }
-    // waveform rows of each type, in the order of that type's items
-    std::vector<int64_t> type_row0(n_types, 0);
-    {
-        int64_t acc = 0;
-        for (int t = 0; t < n_types; ++t) {
-            type_row0[t] = acc;
-            acc += (int64_t)L.type_count[t] * planes[t].n_wires;
-        }
-        rowoff.assign(acc, 0);
-        std::vector<int> rank(n_types, 0);
-        for (int i = 0; i < n_items; ++i) {
-            const int t = items[i].plane_type;
-            const lar_plane& p = planes[t];
-            for (int w = 0; w < p.n_wires; ++w) {
-                int64_t o = items[i].wave_offset + (int64_t)w * p.n_ticks;
-                rowoff[type_row0[t] + (int64_t)rank[t] * p.n_wires + w] = o;
+    for (const Wave& w : L.waves) {
+        row0.push_back((int64_t)rowoff.size());
+        for (int j = 0; j < w.count; ++j) {
+            const int i = w.first + j;
+            const lar_batch_item& it = items[L.order[i]];
+            DevItem& d = dit[i];
+            d.type = it.plane_type;
+            d.slot = j;
+            d.event = it.event;
+            d.plane = it.plane;
+            d.depo_offset = it.depo_offset;
+            d.n_depos = it.n_depos;
+            d.wave_first = w.first;
+            d.pad = 0;
+            const lar_plane& p = planes[it.plane_type];
+            for (int r = 0; r < p.n_wires; ++r) {
+                const int64_t o = it.wave_offset + (int64_t)r * p.n_ticks;
+                rowoff.push_back(o);
                 if (o % 2) even = false;
             }
-            rank[t]++;
         }
     }
-    if (hipMemcpy(W + L.table, tab.data(), sizeof(RasterItem) * n_items, hipMemcpyHostToDevice) !=
-            hipSuccess ||
+    if (hipMemcpy(W + L.items, dit.data(), sizeof(DevItem) * n_items, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W + L.types, dty.data(), sizeof(DevType) * n_types, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(W + L.rowoff, rowoff.data(), sizeof(int64_t) * rowoff.size(), hipMemcpyHostToDevice) !=
             hipSuccess)
         return LAR_EHIP;
 
     lar_batch* b = new (std::nothrow) lar_batch;
     if (!b) return LAR_EINVAL;
+    b->mode = mode;
+    b->planes.assign(planes, planes + n_types);
+    b->resp.assign(resp, resp + n_types);
+    for (int i = 0; i < n_items; ++i) b->items.push_back(items[L.order[i]]);
+    b->waves = L.waves;
+    for (int t = 0; t < n_types; ++t) b->proto.push_back(dty[t].proto);
+    b->depos = *depos;
+    b->arena = W + L.arena;
+    b->dtab = reinterpret_cast<const RasterItem*>(W + L.table);
+    b->drow = reinterpret_cast<const int64_t*>(W + L.rowoff);
+    b->row0 = row0;
+    b->rows_even = even;
+    b->ditp = reinterpret_cast<const DevItem*>(W + L.items);
+    b->dtyp = reinterpret_cast<const DevType*>(W + L.types);
+    b->dpre = reinterpret_cast<int64_t*>(W + L.prefix);
+    b->gsz = L.gsz;
+    b->ssz = L.ssz;
+    b->msz = L.msz;
+
     // ---- the launch sequence
-    const RasterItem* dtab = reinterpret_cast<const RasterItem*>(W + L.table);
-    const int64_t* drow = reinterpret_cast<const int64_t*>(W + L.rowoff);
-    float* grids = reinterpret_cast<float*>(W + L.grids);
-    const int64_t grid_floats = (int64_t)((L.specs - L.grids) / sizeof(float));
-    b->steps.push_back([=](hipStream_t s) { return launch_fill(grids, grid_floats, s); });
-    const RasterItem one = tab[0];
-    const int64_t total_sub = L.total_sub;
-    void* rws = W + L.raster;
-    const size_t rws_bytes = L.total - L.raster;
+    const DevItem* ditp = reinterpret_cast<const DevItem*>(W + L.items);
+    const DevType* dtyp = reinterpret_cast<const DevType*>(W + L.types);
+    RasterItem* dtab = reinterpret_cast<RasterItem*>(W + L.table);
+    int64_t* dpre = reinterpret_cast<int64_t*>(W + L.prefix);
+    const lar_depos dep = *depos;
     b->steps.push_back([=](hipStream_t s) {
-        return launch_raster_items(mode, one, dtab, n_items, total_sub, rws, rws_bytes, s);
+        hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableThreads), 0, s, ditp, dtyp, n_items, dep, dtab,
+                           dpre);
+        return hipGetLastError();
     });
-    for (int t = 0; t < n_types; ++t) {
-        const int k = L.type_count[t];
-        if (!k) continue;
+    void* rws = W + L.raster;
+    const size_t rws_bytes = L.raster_bytes;
+    for (size_t wi = 0; wi < L.waves.size(); ++wi) {
+        const Wave w = L.waves[wi];
+        const int t = w.type, k = w.count;
         const lar_plane p = planes[t];
         const int64_t ld = spec_ld_of(p);
         const int rows = p.n_wires * p.n_imp;
-        const float* g = reinterpret_cast<const float*>(W + L.type_grid[t]);
-        float2* S = reinterpret_cast<float2*>(W + L.type_spec[t]);
-        float2* M = reinterpret_cast<float2*>(W + L.type_mout[t]);
-        const int64_t gstride = (int64_t)(al((size_t)rows * p.n_ticks * sizeof(float)) / sizeof(float));
-        const int64_t sstride = (int64_t)(al((size_t)rows * ld * sizeof(float2)) / sizeof(float2));
-        const int64_t mstride = (int64_t)(al((size_t)p.n_wires * ld * sizeof(float2)) / sizeof(float2));
+        float* g = reinterpret_cast<float*>(W + L.arena);
+        float2* S = reinterpret_cast<float2*>(W + L.arena + L.gsz[t] * k);
+        float2* M = reinterpret_cast<float2*>(W + L.arena + (L.gsz[t] + L.ssz[t]) * k);
+        const int64_t gstride = (int64_t)(L.gsz[t] / sizeof(float));
+        const int64_t sstride = (int64_t)(L.ssz[t] / sizeof(float2));
+        const int64_t mstride = (int64_t)(L.msz[t] / sizeof(float2));
         const float2* R = reinterpret_cast<const float2*>(resp[t]);
         const int F = p.nt_fft / 2 + 1;
         const float scale = (float)(1.0 / ((double)p.nw_fft * (double)p.nt_fft));
-        const int64_t* ro = drow + type_row0[t];
+        const int64_t* ro = b->drow + row0[wi];
         const Sched sc = sched_for(p.n_wires, p.n_imp, p.n_ticks, p.nt_fft, p.nw_fft);
-        // grids of one type are gstride apart: contiguous rows when padded to none
+        const RasterItem* wtab = dtab + w.first;
+        const RasterItem one{};
+        b->steps.push_back([=](hipStream_t s) { return launch_fill(g, gstride * k, s); });
+        if (w.total_sub > 0)
+            b->steps.push_back([=](hipStream_t s) {
+                return launch_raster_items(mode, one, wtab, k, w.total_sub, rws, rws_bytes, s);
+            });
+        // grids of a wave are gstride floats apart: one launch when unpadded
         if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
             b->steps.push_back([=](hipStream_t s) {
-                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s,
-                                       sc.row_threads, sc.row_order);
+                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s, sc.row_threads,
+                                       sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
                 b->steps.push_back([=](hipStream_t s) {
-                    return launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft,
-                                           S + r * sstride, ld, s, sc.row_threads, sc.row_order);
+                    return launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft, S + r * sstride,
+                                           ld, s, sc.row_threads, sc.row_order);
                 });
         }
         b->steps.push_back([=](hipStream_t s) {
-            return launch_wire_fused(S, ld, p.n_wires, p.n_imp, p.nw_fft, F, R, M, ld, s, k, sstride,
-                                     mstride, sc.wire_cols, sc.wire_threads, sc.wire_order);
+            return launch_wire_fused(S, ld, p.n_wires, p.n_imp, p.nw_fft, F, R, M, ld, s, k, sstride, mstride,
+                                     sc.wire_cols, sc.wire_threads, sc.wire_order);
         });
         if (mstride == (int64_t)p.n_wires * ld) {
             b->steps.push_back([=](hipStream_t s) {
-                return launch_c2r_rows(M, ld, p.n_wires * k, p.nt_fft, wave, p.n_ticks, p.n_ticks, scale,
-                                       s, ro, even, sc.row_threads, sc.row_order);
+                return launch_c2r_rows(M, ld, p.n_wires * k, p.nt_fft, wave, p.n_ticks, p.n_ticks, scale, s, ro,
+                                       even, sc.row_threads, sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
                 b->steps.push_back([=](hipStream_t s) {
-                    return launch_c2r_rows(M + r * mstride, ld, p.n_wires, p.nt_fft, wave, p.n_ticks,
-                                           p.n_ticks, scale, s, ro + (int64_t)r * p.n_wires, even,
-                                           sc.row_threads, sc.row_order);
+                    return launch_c2r_rows(M + r * mstride, ld, p.n_wires, p.nt_fft, wave, p.n_ticks, p.n_ticks,
+                                           scale, s, ro + (int64_t)r * p.n_wires, even, sc.row_threads,
+                                           sc.row_order);
                 });
         }
     }
@@ -305,6 +484,15 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
     return LAR_OK;
 }
 
+int lar_batch_waves(const lar_batch* b, int32_t* n_waves, int32_t* max_items) {
+    if (!b) return LAR_EINVAL;
+    int m = 0;
+    for (const Wave& w : b->waves) m = std::max(m, w.count);
+    if (n_waves) *n_waves = (int32_t)b->waves.size();
+    if (max_items) *max_items = m;
+    return LAR_OK;
+}
+
 int lar_batch_run(lar_batch* b, void* stream) {
     if (!b) return LAR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -314,6 +502,72 @@ int lar_batch_run(lar_batch* b, void* stream) {
     }
     for (auto& f : b->steps)
         if (f(s) != hipSuccess) return LAR_EHIP;
+    return LAR_OK;
+}
+
+#define LAR_BTRY(expr)                                            \
+    do {                                                          \
+        if ((expr) != hipSuccess) return ((void)hipGetLastError(), LAR_EHIP); \
+    } while (0)
+
+int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_grad, float* dq, float* dt,
+                       float* dx, float* dsigma_t, float* dsigma_x, void* stream) {
+    if (!b || !wave_grad) return LAR_EINVAL;
+    if (b->mode != 0) return LAR_EINVAL;   // gradients of the mean path only
+    const bool want_depo = dq || dt || dx || dsigma_t || dsigma_x;
+    if (want_depo && !(dq && dt && dx && dsigma_t && dsigma_x)) return LAR_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableThreads), 0, s, b->ditp, b->dtyp, (int)b->items.size(),
+                       b->depos, const_cast<RasterItem*>(b->dtab), b->dpre);
+    LAR_BTRY(hipGetLastError());
+    std::vector<bool> first(b->planes.size(), true);
+    for (size_t wi = 0; wi < b->waves.size(); ++wi) {
+        const Wave& w = b->waves[wi];
+        const int t = w.type, k = w.count;
+        const lar_plane& p = b->planes[t];
+        const int64_t ld = spec_ld_of(p);
+        const int rows = p.n_wires * p.n_imp;
+        float* g = reinterpret_cast<float*>(b->arena);
+        float2* S = reinterpret_cast<float2*>(b->arena + b->gsz[t] * k);
+        float2* M = reinterpret_cast<float2*>(b->arena + (b->gsz[t] + b->ssz[t]) * k);
+        const int64_t gstride = (int64_t)(b->gsz[t] / sizeof(float));
+        const int64_t sstride = (int64_t)(b->ssz[t] / sizeof(float2));
+        const int64_t mstride = (int64_t)(b->msz[t] / sizeof(float2));
+        const float scale = (float)(1.0 / ((double)p.nw_fft * (double)p.nt_fft));
+        const Sched sc = sched_for(p.n_wires, p.n_imp, p.n_ticks, p.nt_fft, p.nw_fft);
+        const int64_t* ro = b->drow + b->row0[wi];
+        float2* dR = resp_grad ? reinterpret_cast<float2*>(resp_grad[t]) : nullptr;
+        // the wave's grids and their time spectra, recomputed (patches are not stored)
+        LAR_BTRY(launch_fill(g, gstride * k, s));
+        if (w.total_sub > 0) {
+            const RasterItem one{};
+            LAR_BTRY(launch_raster_items(0, one, b->dtab + w.first, k, w.total_sub, nullptr, 0, s));
+        }
+        for (int r = 0; r < k; ++r)
+            LAR_BTRY(launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft, S + r * sstride, ld,
+                                     s, sc.row_threads, sc.row_order));
+        // time spectra of the waveform gradients, into the wire-pass buffers
+        for (int r = 0; r < k; ++r)
+            LAR_BTRY(launch_r2c_rows(wave_grad, p.n_ticks, p.n_ticks, p.n_wires, p.nt_fft, M + r * mstride, ld, s,
+                                     sc.row_threads, sc.row_order, ro + (int64_t)r * p.n_wires, b->rows_even));
+        LAR_BTRY(launch_wire_adjoint_items(M, ld, mstride, S, ld, sstride, k, p.n_wires, p.n_imp, p.nw_fft,
+                                           p.nt_fft, reinterpret_cast<const float2*>(b->resp[t]), dR, scale, s,
+                                           !first[t]));
+        first[t] = false;
+        if (!want_depo) continue;
+        for (int r = 0; r < k; ++r)
+            LAR_BTRY(launch_c2r_rows(S + r * sstride, ld, rows, p.nt_fft, g + r * gstride, p.n_ticks, p.n_ticks,
+                                     scale, s, nullptr, false, sc.row_threads, sc.row_order));
+        for (int j = 0; j < k; ++j) {
+            const lar_batch_item& it = b->items[w.first + j];
+            if (it.n_depos == 0) continue;
+            const int64_t o = it.depo_offset;
+            RasterArgs a = b->proto[t];
+            const lar_depos& D = b->depos;
+            LAR_BTRY(launch_raster_bwd(a, D.q + o, D.t + o, D.x + o, D.sigma_t + o, D.sigma_x + o, it.n_depos,
+                                       g + j * gstride, dq + o, dt + o, dx + o, dsigma_t + o, dsigma_x + o, s));
+        }
+    }
     return LAR_OK;
 }
 

@@ -123,7 +123,8 @@ template <int VPT, int NT>
 __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
                                                           int64_t ld_in, int n_in, int nrows,
                                                           FftPlan plan, float2* __restrict__ out,
-                                                          int64_t ld_out, int pairs_ok) {
+                                                          int64_t ld_out, int pairs_ok,
+                                                          const int64_t* __restrict__ row_in) {
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
@@ -131,8 +132,10 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
     fill_half_table(h, Nh, tid, T);
     const TwHalf tw{h, Nh};
     float2 v[VPT];
+    // input row r starts at row_in[r] when given, else at r * ld_in
+    auto row_ptr = [&](int r) { return in + (row_in ? row_in[r] : (int64_t)r * ld_in); };
     int row = blockIdx.x;
-    if (row < nrows) issue_row_pairs<VPT>(in + (int64_t)row * ld_in, n_in, tid, T, pairs_ok != 0, v);
+    if (row < nrows) issue_row_pairs<VPT>(row_ptr(row), n_in, tid, T, pairs_ok != 0, v);
     for (; row < nrows; row += gridDim.x) {
         lds_barrier();
 #pragma unroll
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
         }
         // prefetch the next row of this workgroup while this one is transformed
         if (row + (int)gridDim.x < nrows)
-            issue_row_pairs<VPT>(in + (int64_t)(row + gridDim.x) * ld_in, n_in, tid, T, pairs_ok != 0, v);
+            issue_row_pairs<VPT>(row_ptr(row + gridDim.x), n_in, tid, T, pairs_ok != 0, v);
         lds_barrier();
         fft_lds<VPT, 1>(A, plan, tid, T, tw, false);
         // split step: X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2
@@ -300,7 +303,8 @@ bool row_sched_ok(int nt_fft, int threads, int order) {
 // 4 workgroups per CU.  threads = 0 selects the default: 256 threads for
 // half-lengths up to 1024, 512 up to 4096 and 1024 above.
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
-                           float2* out, int64_t ld_out, hipStream_t s, int threads, int order) {
+                           float2* out, int64_t ld_out, hipStream_t s, int threads, int order,
+                           const int64_t* row_in, bool row_in_even) {
     if (!threads) threads = default_row_threads(nt_fft);
     FftPlan plan;
     if (!make_plan(nt_fft / 2, &plan, order)) return hipErrorInvalidValue;
@@ -308,14 +312,16 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
     if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
     const size_t lds = 2 * (size_t)Nh * sizeof(float2);
-    const int pairs_ok =
-        ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0) ? 1 : 0;
+    const int pairs_ok = ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0 &&
+                          (row_in == nullptr || row_in_even))
+                             ? 1
+                             : 0;
     dim3 grid(row_grid(nrows));
 #define LAR_R2C(V, T)                                                                           \
     {                                                                                           \
         set_lds(k_r2c_rows<V, T>, lds);                                                         \
         hipLaunchKernelGGL((k_r2c_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, n_in, nrows,   \
-                           plan, out, ld_out, pairs_ok);                                        \
+                           plan, out, ld_out, pairs_ok, row_in);                                \
     }
     LAR_ROW_DISPATCH(vpt, threads, LAR_R2C)
 #undef LAR_R2C
@@ -365,17 +371,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_wire_fused(
     const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
     const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
-    int64_t strideM) {
+    int64_t strideM, int batch) {
     extern __shared__ float2 lds[];
-    // blockIdx.y: item of a batch sharing this plane shape and response
-    S += (int64_t)blockIdx.y * strideS;
-    M += (int64_t)blockIdx.y * strideM;
+    // block -> (tile, item) of a batch sharing this plane shape and response:
+    // consecutive linear indices run on one XCD, items fastest, so the
+    // blocks of one tile for every item run together and read the tile's
+    // response slabs from that XCD's L2 (one HBM read per tile and batch)
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = lin / batch, item = lin - tile * batch;
+    S += (int64_t)item * strideS;
+    M += (int64_t)item * strideM;
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;               // [Wf][C]
     float2* tw = lds + Wf * C;     // [Wf]
     fill_full_table(tw, Wf, tid, T);
     const TwFull twf{tw};
-    const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const int f0 = tile * C;
     const int nel = Wf * C;
     float2 acc[VPT];
 #pragma unroll
@@ -463,9 +474,9 @@ static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_i
                               int batch, int64_t strideS, int64_t strideM, hipStream_t s) {
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     set_lds(k_wire_fused<VPT, C, NT>, lds);
-    dim3 grid((F + C - 1) / C, batch), block(NT);
+    dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(NT);
     hipLaunchKernelGGL((k_wire_fused<VPT, C, NT>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
-                       plan, R, M, ldM, strideS, strideM);
+                       plan, R, M, ldM, strideS, strideM, batch);
     return hipGetLastError();
 }
 
@@ -657,6 +668,142 @@ hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, const float2* S, i
         return wire_adj_launch<8, 8, 1024>(Gt, ldG, S, ldS, O, ldO, n_wires, n_imp, F, nyq, plan, R,
                                            dR, want_grid, resp_scale, accumulate, s);
 #undef LAR_WADJ
+    return hipErrorInvalidValue;
+}
+
+// The adjoint wire pass over a batch of items sharing one response (the
+// batch plan's backward): per tile and impact offset k, the items are the
+// inner loop, so the response-spectrum gradient of the tile is summed over
+// the batch in registers and read-modify-written once per k, and R[k] is
+// read once per tile.  Each item's Gh is the wire FFT of its Gt tile,
+// recomputed per k (its rows are re-read from L2) rather than held for
+// every item.  The grid-gradient spectrum of item b is written over its S
+// rows (each tile reads them first).  Item b's arrays are at Gt + b*strideG
+// and S + b*strideS.
+template <int VPT, int C, int NT>
+__global__ __launch_bounds__(NT) void k_wire_adjoint_items(
+    const float2* __restrict__ Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS, int64_t strideS,
+    int batch, int n_wires, int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R,
+    float2* __restrict__ dR, float resp_scale, int accumulate) {
+    extern __shared__ float2 lds[];
+    const int Wf = plan.n, tid = threadIdx.x, T = NT;
+    float2* A = lds;
+    float2* tw = lds + Wf * C;
+    fill_full_table(tw, Wf, tid, T);
+    const TwFull twf{tw};
+    const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const int nel = Wf * C;
+    // load a [wire][column] tile of rows p * rstride + off into A (zero outside)
+    auto load_tile = [&](const float2* base, int64_t ld, int rstride, int off, int rows) {
+        float2 v[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + i * T;
+            const int p = e / C, f = f0 + e % C;
+            const bool ok = e < nel && p < rows && f < F;
+            const float2 x = base[(int64_t)(min(p, rows - 1) * rstride + off) * ld + min(f, F - 1)];
+            v[i] = ok ? x : make_float2(0.f, 0.f);
+        }
+        lds_barrier();
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + i * T;
+            if (e < nel) A[e] = v[i];
+        }
+        lds_barrier();
+    };
+    for (int k = 0; k < n_imp; ++k) {
+        float2 dacc[VPT], r[VPT];
+        const float2* Rk = R + (int64_t)k * Wf * F;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            dacc[i] = make_float2(0.f, 0.f);
+            const int e = tid + i * T;
+            const int p = min(e / C, Wf - 1), f = min(f0 + e % C, F - 1);
+            r[i] = Rk[(int64_t)p * F + f];
+        }
+        for (int b = 0; b < batch; ++b) {
+            const float2* Gb = Gt + (int64_t)b * strideG;
+            float2* Sb = S + (int64_t)b * strideS;
+            float2 gh[VPT];
+            load_tile(Gb, ldG, 1, 0, n_wires);
+            fft_lds<VPT, C>(A, plan, tid, T, twf, false);
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                if (e < nel) gh[i] = A[e];
+            }
+            if (dR) {
+                load_tile(Sb, ldS, n_imp, k, n_wires);
+                fft_lds<VPT, C>(A, plan, tid, T, twf, false);
+#pragma unroll
+                for (int i = 0; i < VPT; ++i) {
+                    const int e = tid + i * T;
+                    if (e < nel) {
+                        const float2 g = cmulc(gh[i], A[e]);   // Gh conj(Sk)
+                        dacc[i].x += g.x;
+                        dacc[i].y += g.y;
+                    }
+                }
+            }
+            lds_barrier();
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                if (e < nel) A[e] = cmulc(gh[i], r[i]);   // conj(R) Gh
+            }
+            lds_barrier();
+            fft_lds<VPT, C>(A, plan, tid, T, twf, true);
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = e / C, f = f0 + e % C;
+                if (e < nel && p < n_wires && f < F) Sb[(int64_t)(p * n_imp + k) * ldS + f] = A[e];
+            }
+        }
+        if (dR) {
+            float2* dRk = dR + (int64_t)k * Wf * F;
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int e = tid + i * T;
+                const int p = e / C, f = f0 + e % C;
+                if (e < nel && f < F) {
+                    const float cf = (f == 0 || f == nyq) ? resp_scale : 2.f * resp_scale;
+                    float2* o = dRk + (int64_t)p * F + f;
+                    float2 cur = accumulate ? *o : make_float2(0.f, 0.f);
+                    cur.x += cf * dacc[i].x;
+                    cur.y += cf * dacc[i].y;
+                    *o = cur;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS,
+                                     int64_t strideS, int batch, int n_wires, int n_imp, int nw_fft,
+                                     int nt_fft, const float2* R, float2* dR, float resp_scale,
+                                     hipStream_t s, bool accumulate) {
+    FftPlan plan;
+    if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
+    if (batch <= 0) return hipSuccess;
+    const int F = nt_fft / 2 + 1, nyq = nt_fft / 2;
+    constexpr int C = 8;
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
+    dim3 grid((F + C - 1) / C);
+#define LAR_WADJI(V, NT)                                                                                \
+    {                                                                                                   \
+        set_lds(k_wire_adjoint_items<V, C, NT>, lds);                                                   \
+        hipLaunchKernelGGL((k_wire_adjoint_items<V, C, NT>), grid, dim3(NT), lds, s, Gt, ldG, strideG, S, \
+                           ldS, strideS, batch, n_wires, n_imp, F, nyq, plan, R, dR, resp_scale,        \
+                           accumulate ? 1 : 0);                                                         \
+        return hipGetLastError();                                                                       \
+    }
+    if (nw_fft <= 128) LAR_WADJI(2, 512)
+    if (nw_fft <= 256) LAR_WADJI(4, 512)
+    if (nw_fft <= 512) LAR_WADJI(8, 512)
+    if (nw_fft <= 1024) LAR_WADJI(8, 1024)
+#undef LAR_WADJI
     return hipErrorInvalidValue;
 }
 

@@ -249,9 +249,11 @@ bool wire_sched_ok(int nw_fft, int cols, int threads, int order);
 // The schedule registered for this plane shape, else the default one.
 Sched sched_for(int n_wires, int n_imp, int n_ticks, int nt_fft, int nw_fft);
 
+// row_in (device, optional): input offset of each row (else row * ld_in);
+// the pair loads then need every offset even (row_in_even).
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
                            float2* out, int64_t ld_out, hipStream_t s, int threads = 0,
-                           int order = 0);
+                           int order = 0, const int64_t* row_in = nullptr, bool row_in_even = false);
 // row_off (device, optional): output offset of each row (else row * ld_out);
 // the even-pair stores then need every offset even.
 hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_fft, float* out,
@@ -291,7 +293,8 @@ struct RasterItem {
 // kDeferredBytes-byte deferred bins (capacity = the remaining bytes /
 // kDeferredBytes; any capacity, zero included, gives the same result).  The
 // mean raster needs none.
-int64_t raster_subchunks(int64_t n);
+constexpr int kRasterSub = 16;   // depos per sub-chunk (one wave's unit of raster work)
+__host__ __device__ inline int64_t raster_subchunks(int64_t n) { return (n + kRasterSub - 1) / kRasterSub; }
 size_t raster_ws_fixed_subs(int64_t nsub);
 size_t raster_ws_fixed(int64_t n);
 constexpr size_t kDeferredBytes = 16;
@@ -333,6 +336,13 @@ hipError_t launch_noise_spectrum(const float* amp, int F, int n_wires, uint64_t 
                                  uint32_t plane, float2* X, int64_t ld, hipStream_t s);
 hipError_t launch_digitize(const float* wave, const float* noise, int64_t n, float gain, float baseline,
                            int bits, uint16_t* out, hipStream_t s);
+// Adjoint wire pass over `batch` items sharing R (item b at Gt + b*strideG,
+// S + b*strideS): grid-gradient spectra written over S; dR = (or +=, with
+// accumulate) the gradient summed over the items.
+hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS,
+                                     int64_t strideS, int batch, int n_wires, int n_imp, int nw_fft,
+                                     int nt_fft, const float2* R, float2* dR, float resp_scale,
+                                     hipStream_t s, bool accumulate);
 hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
                                 const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                                 hipStream_t s);

@@ -807,7 +807,7 @@ __device__ __forceinline__ float single_weight(double mu, double sg, double org,
 
 static constexpr int kRasterThreads = 256;
 static constexpr int kWaves = kRasterThreads / 64;
-static constexpr int kSub = 16;           // depos per wave sub-chunk
+static constexpr int kSub = kRasterSub;   // depos per wave sub-chunk
 static constexpr int kMaxT = 16;          // window limits of the LDS slots (bins)
 static constexpr int kMaxX = 32;
 static constexpr int kSlot = kMaxT + kMaxX + 1;
@@ -854,8 +854,6 @@ static constexpr uint32_t kInvMark = 0x08000000u;    // ... an inversion bin (el
 // sub-chunk flag bits (one byte per sub-chunk, cleared by k_raster_reset)
 static constexpr int kFlagOverflow = 1;   // some of its deferred bins did not fit in the queue
 static constexpr int kFlagWide = 2;       // it holds a depo wider than the weight slots
-
-int64_t raster_subchunks(int64_t n) { return (n + kSub - 1) / kSub; }
 
 size_t raster_ws_fixed_subs(int64_t nsub) { return 256 + (((size_t)nsub + 255) / 256) * 256; }
 

@@ -97,6 +97,10 @@ SIGNATURES = {
                              _P(_SZ)], ctypes.c_int),
     "lar_batch_create": ([_P(lar_plane), ctypes.c_int32, _P(_VP), _P(lar_depos), ctypes.c_float, _P(lar_fluct),
                           _P(lar_batch_item), ctypes.c_int32, _VP, _VP, _SZ, ctypes.c_int32, _P(_VP)], ctypes.c_int),
+    "lar_batch_workspace_waves": ([_P(lar_plane), ctypes.c_int32, _P(lar_batch_item), ctypes.c_int32,
+                                   _P(lar_fluct), ctypes.c_int32, _P(_SZ)], ctypes.c_int),
+    "lar_batch_waves": ([_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
+    "lar_batch_backward": ([_VP, _VP, _P(_VP), _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "lar_batch_run": ([_VP, _VP], ctypes.c_int),
     "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
@@ -441,12 +445,13 @@ def make_items(items):
     return arr
 
 
-def batch_workspace(planes, items, fluct=None) -> int:
+def batch_workspace(planes, items, fluct=None, max_wave=0) -> int:
+    """Workspace for waves of at most max_wave items per plane type (0: all)."""
     pls = (lar_plane * len(planes))(*[make_plane(p) for p in planes])
     its = make_items(items)
     n = ctypes.c_size_t(0)
-    _check(_lib().lar_batch_workspace(pls, len(planes), its, len(its), _fluct(fluct), ctypes.byref(n)),
-           "lar_batch_workspace")
+    _check(_lib().lar_batch_workspace_waves(pls, len(planes), its, len(its), _fluct(fluct), int(max_wave),
+                                            ctypes.byref(n)), "lar_batch_workspace_waves")
     return n.value
 
 
@@ -468,6 +473,21 @@ class Batch:
 
     def run(self, stream=None):
         _check(_lib().lar_batch_run(self._h, _stream(stream)), "lar_batch_run")
+
+    def waves(self):
+        """(number of waves, items in the largest wave)."""
+        n, m = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib().lar_batch_waves(self._h, ctypes.byref(n), ctypes.byref(m)), "lar_batch_waves")
+        return n.value, m.value
+
+    def backward(self, wave_grad, resp_grads=None, depo_grads=None, stream=None):
+        """resp_grads: one tensor per plane type (or None); depo_grads: five
+        tensors in the depo layout (dq, dt, dx, dsigma_t, dsigma_x) or None."""
+        rg = None
+        if resp_grads is not None:
+            rg = (ctypes.c_void_p * len(resp_grads))(*[None if r is None else r.data_ptr() for r in resp_grads])
+        dg = [None] * 5 if depo_grads is None else [_ptr(d) for d in depo_grads]
+        _check(_lib().lar_batch_backward(self._h, _ptr(wave_grad), rg, *dg, _stream(stream)), "lar_batch_backward")
 
     def close(self):
         if self._h:

@@ -1,8 +1,13 @@
-"""Batched plan (one persistent raster launch, per-type batched FFT stages,
-hipGraph replay) against per-item lar_sim_plane runs."""
+"""Batched plan (items per plane type in waves: one raster launch and one
+launch per FFT stage per wave, hipGraph replay) against per-item
+lar_sim_plane runs and against the FP64 oracle at the three-plane geometry
+(800-wire bipolar induction planes, Wf 864, and the 480-wire collection
+plane, 6000 ticks); the batched backward against the oracle's gradients
+summed over items."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2203_02479_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -47,13 +52,18 @@ def _reference(torch, lar, planes, resps, items, deps, fl, total):
     return ref.cpu().numpy()
 
 
-@pytest.mark.parametrize("mode,use_graph", [(1, True), (1, False), (2, True), (0, True)])
-def test_batch_matches_single_plane_runs(mode, use_graph):
+@pytest.mark.parametrize("mode,use_graph,max_wave", [(1, True, 0), (1, False, 0), (2, True, 0), (0, True, 0),
+                                                    (1, True, 1), (3, True, 2), (0, True, 2)])
+def test_batch_matches_single_plane_runs(mode, use_graph, max_wave):
     torch, lar, planes, resps, items, deps, cat, fl, total = _setup(fluct_mode=mode)
     D = lar.DeviceDepos.from_host(cat)
     wave = torch.full((total,), -7.0, device="cuda")
-    ws = lar.workspace(lar.batch_workspace(planes, items, fl))
+    ws = lar.workspace(lar.batch_workspace(planes, items, fl, max_wave=max_wave))
     b = lar.Batch(planes, resps, D, 3.0, fl, items, wave, ws, use_graph=use_graph)
+    n_waves, largest = b.waves()
+    # 3 events: 6 items of type 0, 3 of type 1
+    assert largest == (6 if max_wave == 0 else max_wave)
+    assert n_waves == (2 if max_wave == 0 else -(-6 // max_wave) - (-3 // max_wave))
     ref = _reference(torch, lar, planes, resps, items, deps, fl, total)
     for rep in range(3):
         wave.fill_(-7.0)                 # eager work between replays
@@ -103,3 +113,141 @@ def test_batch_with_wide_depos(mode):
     else:
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-5 * np.abs(ref).max())
     b.close()
+
+
+# ------------------------------------------------------------------ oracle parity at full geometry
+
+def rel_l2(a, b):
+    cplx = np.iscomplexobj(a) or np.iscomplexobj(b)    # complex arrays keep their imaginary part
+    a = np.asarray(a, np.complex128 if cplx else np.float64)
+    b = np.asarray(b, np.complex128 if cplx else np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _three_plane_batch(n_events, n_track, n_points, seed0):
+    """Events of the three-plane geometry (U, V: 800 wires, bipolar, Wf 864;
+    W: 480 wires, unipolar; 6000 ticks) as batch items of two plane types."""
+    import torch
+    from paper_2203_02479_amd import lar
+    evs = [inputs.cfg2_event(seed=seed0 + e, n_track=n_track, n_points=n_points, n_seg=max(1, n_track // 8333))
+           for e in range(n_events)]
+    planes = [evs[0].planes[0], evs[0].planes[2]]
+    rtime = [inputs.response_time(p.n_imp, p.half_w, inputs.RESP_TICKS, p.kind) for p in planes]
+    resps = [lar.spectrum_from_time(p, r) for p, r in zip(planes, rtime)]
+    items, chunks, off, woff = [], [], 0, 0
+    for e, ev in enumerate(evs):
+        for pl in range(3):
+            pt = 0 if pl < 2 else 1
+            d = ev.depos[pl]
+            items.append((pt, e, pl, off, len(d), woff))
+            chunks.append(d)
+            off += len(d)
+            woff += planes[pt].n_wires * planes[pt].n_ticks
+    cat = inputs.Depos(*(np.concatenate([c.arrays()[k] for c in chunks]) for k in range(5)))
+    return torch, lar, planes, rtime, resps, items, chunks, cat, woff
+
+
+@pytest.mark.parametrize("mode,max_wave", [(0, 0), (1, 2)])
+def test_batch_three_planes_vs_oracle(mode, max_wave):
+    """Each item's waveforms against the oracle: the mean path within
+    relative L2 1e-5 and max |diff| 1e-5 of max |ref|; fluctuated items
+    against the oracle's convolution of its fluctuated grid under the same
+    keys (nearly every bin identical: relative L2 1e-4)."""
+    torch, lar, planes, rtime, resps, items, chunks, cat, total = _three_plane_batch(2, 40_000, 2_000,
+                                                                                    inputs.SEED0 + 600)
+    fl = (mode, 555, 0, 0) if mode else None
+    D = lar.DeviceDepos.from_host(cat)
+    wave = torch.full((total,), float("nan"), device="cuda")
+    ws = lar.workspace(lar.batch_workspace(planes, items, fl, max_wave=max_wave))
+    b = lar.Batch(planes, resps, D, inputs.NSIGMA, fl, items, wave, ws)
+    b.run()
+    torch.cuda.synchronize()
+    got_all = wave.cpu().numpy()
+    b.close()
+    Rc = [oracle.response_spectrum(p, r) for p, r in zip(planes, rtime)]
+    for (pt, e, pl, off, n, wo), d in zip(items, chunks):
+        P = planes[pt]
+        got = got_all[wo:wo + P.n_wires * P.n_ticks].reshape(P.n_wires, P.n_ticks)
+        if mode == 0:
+            ref = oracle.sim_plane_mean(P, d, Rc[pt])
+            assert rel_l2(got, ref) < 1e-5, (e, pl)
+            assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), (e, pl)
+        else:
+            S = oracle.raster_fluct(P, d, inputs.NSIGMA, mode=mode, seed=555, event=e, plane_id=pl)
+            ref = oracle.conv_fft(P, S, Rc[pt])
+            assert rel_l2(got, ref) < 1e-4, (e, pl)
+
+
+def test_full_three_plane_event_vs_oracle():
+    """One full event of the three-plane configuration (1.9M track depos and
+    100k point depos with q log-uniform in 1e2..1e5) through lar_sim_plane
+    per plane: mean waveforms within relative L2 1e-5 and max |diff| 1e-5 of
+    max |ref|; binomial grids with at least 99.99% of the non-zero bins equal
+    to the oracle's."""
+    import torch
+    from paper_2203_02479_amd import lar
+    ev = inputs.cfg2_event()
+    for pl in range(3):
+        P, dep = ev.planes[pl], ev.depos[pl]
+        r = inputs.response_time(P.n_imp, P.half_w, inputs.RESP_TICKS, P.kind)
+        D = lar.DeviceDepos.from_host(dep)
+        resp = lar.spectrum_from_time(P, r)
+        wave = torch.empty((P.n_wires, P.n_ticks), device="cuda")
+        lar.sim_plane(P, D, inputs.NSIGMA, None, resp, wave, lar.workspace(lar.sim_plane_workspace(P)))
+        torch.cuda.synchronize()
+        got = wave.cpu().numpy()
+        ref = oracle.sim_plane_mean(P, dep, oracle.response_spectrum(P, r))
+        assert rel_l2(got, ref) < 1e-5, pl
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), pl
+        del wave
+        fl = (1, inputs.SEED0 + 200, 0, pl)
+        grid = torch.zeros((P.n_rows, P.n_ticks), device="cuda")
+        lar.raster(P, D, inputs.NSIGMA, fl, grid, lar.workspace(lar.raster_workspace(P, len(dep), fl)))
+        torch.cuda.synchronize()
+        g = grid.cpu().numpy()
+        del grid
+        S = oracle.raster_fluct(P, dep, inputs.NSIGMA, mode=1, seed=inputs.SEED0 + 200, event=0, plane_id=pl)
+        nz = (g != 0) | (S != 0)
+        assert np.mean(g[nz] == S[nz]) > 0.9999, pl
+        assert abs(g.sum() - S.sum()) < 1e-4 * abs(S.sum())
+
+
+def test_batch_backward_vs_oracle():
+    """The batched backward (waves of 2 items, so the response gradient
+    accumulates across waves) against the oracle: grid-path gradients per
+    item (conv_adjoint then raster_adjoint) and the response gradient summed
+    over the items of each plane type, relative L2 1e-4 each."""
+    torch, lar, planes, rtime, resps, items, chunks, cat, total = _three_plane_batch(2, 20_000, 1_000,
+                                                                                    inputs.SEED0 + 700)
+    # one item without depos
+    pt, e, pl, off, n, wo = items[1]
+    items[1] = (pt, e, pl, off, 0, wo)
+    D = lar.DeviceDepos.from_host(cat)
+    wave = torch.empty(total, device="cuda")
+    ws = lar.workspace(lar.batch_workspace(planes, items, None, max_wave=2))
+    b = lar.Batch(planes, resps, D, inputs.NSIGMA, None, items, wave, ws)
+    assert b.waves() == (3, 2)
+    G = np.random.default_rng(5).standard_normal(total).astype(np.float32)
+    rg = [torch.full_like(r, float("nan")) for r in resps]
+    dg = [torch.full((len(cat),), float("nan"), device="cuda") for _ in range(5)]
+    b.backward(torch.as_tensor(G).cuda(), rg, dg)
+    torch.cuda.synchronize()
+    b.close()
+    Rc = [oracle.response_spectrum(p, r) for p, r in zip(planes, rtime)]
+    dR_ref = [np.zeros_like(R) for R in Rc]
+    dg_np = [d.cpu().numpy() for d in dg]
+    for (pt, e, pl, off, n, wo), d in zip(items, chunks):
+        P = planes[pt]
+        d = d.take(slice(0, n))
+        S = oracle.raster_mean(P, d, inputs.NSIGMA)
+        Gi = G[wo:wo + P.n_wires * P.n_ticks].reshape(P.n_wires, P.n_ticks).astype(np.float64)
+        GS, dR = oracle.conv_adjoint(P, S, Rc[pt], Gi)
+        dR_ref[pt] += dR
+        if n == 0:
+            continue
+        ref = oracle.raster_adjoint(P, d, inputs.NSIGMA, GS)
+        for k, name in enumerate(("q", "t", "x", "sigma_t", "sigma_x")):
+            assert rel_l2(dg_np[k][off:off + n], ref[k]) < 1e-4, (e, pl, name)
+    for t in range(2):
+        got = rg[t].cpu().numpy().astype(np.float64)
+        assert rel_l2(got[..., 0] + 1j * got[..., 1], dR_ref[t]) < 1e-4, t
