@@ -346,8 +346,11 @@ int lar_batch_run(lar_batch *plan, void *stream);
 /* Backward of a mean-path plan (fluct NULL or mode 0; LAR_EINVAL
  * otherwise), the batched form of lar_fftconv_backward + lar_raster_backward
  * (no paper counterpart): for L with dL/dwave = wave_grad (the layout of
- * wave), per wave of items: the grids and their time spectra are
- * recomputed (patches are not stored), the waveform gradients transformed,
+ * wave), per wave of items, last wave first: the grids and their time
+ * spectra are recomputed (patches are not stored) -- except for the last
+ * wave when lar_batch_run was the plan's previous call (its spectra are
+ * still in the workspace; both calls on the same stream) --, the waveform
+ * gradients transformed,
  * the adjoint wire pass runs over the wave's items with the response
  * gradient of each tile summed over the items in registers, then the grid
  * gradients and the depo gradients.
@@ -362,6 +365,28 @@ int lar_batch_run(lar_batch *plan, void *stream);
 int lar_batch_backward(lar_batch *plan, const float *wave_grad, float *const *resp_grad, float *dq,
                        float *dt, float *dx, float *dsigma_t, float *dsigma_x, void *stream);
 int lar_batch_destroy(lar_batch *plan);
+
+/* ---------------------------------------------------------------- streams
+ * Independent plane simulations sharing one GPU through several HIP
+ * streams (the single-GPU form of the paper's several processes per GPU,
+ * Sec. 3.3 and Fig. 4): item i (a lar_batch_item record) runs as
+ * lar_sim_plane on its depos (depo_offset, n_depos) with fluct {mode,
+ * item.event, item.plane, seed}, writing [n_wires][n_ticks] floats at
+ * wave + wave_offset, on streams[i mod n_streams] with workspace slice
+ * i mod n_streams.  The worker streams first wait for the work already on
+ * `stream`, and `stream` then waits for them, so the call is ordered like
+ * any other call on `stream`.  streams: 1..64 distinct hipStream_t, none
+ * equal to `stream`, created by the caller (default priority).  Results
+ * equal per-item lar_sim_plane calls (fluctuated counts exactly).
+ * Workspace: lar_sim_streams_workspace (n_streams slices of the largest
+ * item's lar_sim_plane workspace).  Events are created on the first call
+ * of each host thread and kept. */
+int lar_sim_streams_workspace(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
+                              int32_t n_items, const lar_fluct *fluct, int32_t n_streams, size_t *bytes);
+int lar_sim_streams(const lar_plane *planes, int32_t n_types, const float *const *resp,
+                    const lar_depos *depos, float nsigma, const lar_fluct *fluct,
+                    const lar_batch_item *items, int32_t n_items, float *wave, void *const *streams,
+                    int32_t n_streams, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- schedules
  * Launch schedule of the FFT convolution for one plane shape (no paper

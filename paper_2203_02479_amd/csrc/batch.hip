@@ -242,6 +242,9 @@ struct lar_batch {
     const DevType* dtyp = nullptr;
     int64_t* dpre = nullptr;
     bool rows_even = false;
+    // wave whose time spectra the arena still holds (the last wave of the
+    // last run), -1 when none: the backward pass reuses them
+    int kept_wave = -1;
     std::vector<int64_t> row0;           // per wave: first output row in drow
     std::vector<size_t> gsz, ssz, msz;
 };
@@ -496,12 +499,15 @@ int lar_batch_waves(const lar_batch* b, int32_t* n_waves, int32_t* max_items) {
 int lar_batch_run(lar_batch* b, void* stream) {
     if (!b) return LAR_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    b->kept_wave = -1;
     if (b->exec) {
         hipError_t e = hipGraphLaunch(b->exec, s);
-        return e == hipSuccess ? LAR_OK : ((void)hipGetLastError(), LAR_EHIP);
+        if (e != hipSuccess) return ((void)hipGetLastError(), LAR_EHIP);
+    } else {
+        for (auto& f : b->steps)
+            if (f(s) != hipSuccess) return LAR_EHIP;
     }
-    for (auto& f : b->steps)
-        if (f(s) != hipSuccess) return LAR_EHIP;
+    b->kept_wave = (int)b->waves.size() - 1;
     return LAR_OK;
 }
 
@@ -521,7 +527,10 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
                        b->depos, const_cast<RasterItem*>(b->dtab), b->dpre);
     LAR_BTRY(hipGetLastError());
     std::vector<bool> first(b->planes.size(), true);
-    for (size_t wi = 0; wi < b->waves.size(); ++wi) {
+    // last wave first: right after lar_batch_run its spectra are still in the arena
+    const int kept = b->kept_wave;
+    b->kept_wave = -1;
+    for (int wi = (int)b->waves.size() - 1; wi >= 0; --wi) {
         const Wave& w = b->waves[wi];
         const int t = w.type, k = w.count;
         const lar_plane& p = b->planes[t];
@@ -537,27 +546,48 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
         const Sched sc = sched_for(p.n_wires, p.n_imp, p.n_ticks, p.nt_fft, p.nw_fft);
         const int64_t* ro = b->drow + b->row0[wi];
         float2* dR = resp_grad ? reinterpret_cast<float2*>(resp_grad[t]) : nullptr;
-        // the wave's grids and their time spectra, recomputed (patches are not stored)
-        LAR_BTRY(launch_fill(g, gstride * k, s));
-        if (w.total_sub > 0) {
-            const RasterItem one{};
-            LAR_BTRY(launch_raster_items(0, one, b->dtab + w.first, k, w.total_sub, nullptr, 0, s));
+        // the wave's grids and their time spectra, recomputed (patches are not
+        // stored) unless the forward run left them in the arena
+        if (wi != kept) {
+            LAR_BTRY(launch_fill(g, gstride * k, s));
+            if (w.total_sub > 0) {
+                const RasterItem one{};
+                LAR_BTRY(launch_raster_items(0, one, b->dtab + w.first, k, w.total_sub, nullptr, 0, s));
+            }
+            if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
+                LAR_BTRY(launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s, sc.row_threads,
+                                         sc.row_order));
+            } else {
+                for (int r = 0; r < k; ++r)
+                    LAR_BTRY(launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft, S + r * sstride,
+                                             ld, s, sc.row_threads, sc.row_order));
+            }
         }
-        for (int r = 0; r < k; ++r)
-            LAR_BTRY(launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft, S + r * sstride, ld,
-                                     s, sc.row_threads, sc.row_order));
         // time spectra of the waveform gradients, into the wire-pass buffers
-        for (int r = 0; r < k; ++r)
-            LAR_BTRY(launch_r2c_rows(wave_grad, p.n_ticks, p.n_ticks, p.n_wires, p.nt_fft, M + r * mstride, ld, s,
-                                     sc.row_threads, sc.row_order, ro + (int64_t)r * p.n_wires, b->rows_even));
+        if (mstride == (int64_t)p.n_wires * ld) {
+            LAR_BTRY(launch_r2c_rows(wave_grad, p.n_ticks, p.n_ticks, p.n_wires * k, p.nt_fft, M, ld, s,
+                                     sc.row_threads, sc.row_order, ro, b->rows_even));
+        } else {
+            for (int r = 0; r < k; ++r)
+                LAR_BTRY(launch_r2c_rows(wave_grad, p.n_ticks, p.n_ticks, p.n_wires, p.nt_fft, M + r * mstride, ld,
+                                         s, sc.row_threads, sc.row_order, ro + (int64_t)r * p.n_wires,
+                                         b->rows_even));
+        }
+        // the wave's grids are dead until the grid gradients: scratch for the
+        // response-gradient partials of the item groups
         LAR_BTRY(launch_wire_adjoint_items(M, ld, mstride, S, ld, sstride, k, p.n_wires, p.n_imp, p.nw_fft,
                                            p.nt_fft, reinterpret_cast<const float2*>(b->resp[t]), dR, scale, s,
-                                           !first[t]));
+                                           !first[t], g, b->gsz[t] * k));
         first[t] = false;
         if (!want_depo) continue;
-        for (int r = 0; r < k; ++r)
-            LAR_BTRY(launch_c2r_rows(S + r * sstride, ld, rows, p.nt_fft, g + r * gstride, p.n_ticks, p.n_ticks,
-                                     scale, s, nullptr, false, sc.row_threads, sc.row_order));
+        if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
+            LAR_BTRY(launch_c2r_rows(S, ld, rows * k, p.nt_fft, g, p.n_ticks, p.n_ticks, scale, s, nullptr, false,
+                                     sc.row_threads, sc.row_order));
+        } else {
+            for (int r = 0; r < k; ++r)
+                LAR_BTRY(launch_c2r_rows(S + r * sstride, ld, rows, p.nt_fft, g + r * gstride, p.n_ticks, p.n_ticks,
+                                         scale, s, nullptr, false, sc.row_threads, sc.row_order));
+        }
         for (int j = 0; j < k; ++j) {
             const lar_batch_item& it = b->items[w.first + j];
             if (it.n_depos == 0) continue;

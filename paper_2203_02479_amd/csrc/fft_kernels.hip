@@ -674,24 +674,35 @@ hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, const float2* S, i
 // The adjoint wire pass over a batch of items sharing one response (the
 // batch plan's backward): per tile and impact offset k, the items are the
 // inner loop, so the response-spectrum gradient of the tile is summed over
-// the batch in registers and read-modify-written once per k, and R[k] is
-// read once per tile.  Each item's Gh is the wire FFT of its Gt tile,
-// recomputed per k (its rows are re-read from L2) rather than held for
-// every item.  The grid-gradient spectrum of item b is written over its S
-// rows (each tile reads them first).  Item b's arrays are at Gt + b*strideG
-// and S + b*strideS.
+// the items in registers and written once per k, and R[k] is read once per
+// tile.  The items are split into `groups` consecutive ranges, one block per
+// (tile, group) (groups of one tile run together on one XCD); with one group
+// the sum goes to dR (= or += with accumulate), else group g writes its sum
+// to part + g * part_stride, for k_sum_parts.  Each item's Gh is the wire
+// FFT of its Gt tile, recomputed per k (its rows are re-read from L2) rather
+// than held for every item.  The grid-gradient spectrum of item b is
+// written over its S rows (each tile reads them first).  Item b's arrays are
+// at Gt + b*strideG and S + b*strideS.
 template <int VPT, int C, int NT>
 __global__ __launch_bounds__(NT) void k_wire_adjoint_items(
     const float2* __restrict__ Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS, int64_t strideS,
-    int batch, int n_wires, int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R,
-    float2* __restrict__ dR, float resp_scale, int accumulate) {
+    int batch, int groups, int n_wires, int n_imp, int F, int nyq, FftPlan plan, const float2* __restrict__ R,
+    float2* __restrict__ dR, float2* __restrict__ part, int64_t part_stride, float resp_scale, int accumulate) {
     extern __shared__ float2 lds[];
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
     float2* tw = lds + Wf * C;
     fill_full_table(tw, Wf, tid, T);
     const TwFull twf{tw};
-    const int f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = lin / groups, grp = lin - tile * groups;
+    const int per = (batch + groups - 1) / groups;
+    const int b0 = grp * per, b1 = min(batch, b0 + per);
+    if (groups > 1 && dR) {
+        dR = part + (int64_t)grp * part_stride;
+        accumulate = 0;
+    }
+    const int f0 = tile * C;
     const int nel = Wf * C;
     // load a [wire][column] tile of rows p * rstride + off into A (zero outside)
     auto load_tile = [&](const float2* base, int64_t ld, int rstride, int off, int rows) {
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint_items(
             const int p = min(e / C, Wf - 1), f = min(f0 + e % C, F - 1);
             r[i] = Rk[(int64_t)p * F + f];
         }
-        for (int b = 0; b < batch; ++b) {
+        for (int b = b0; b < b1; ++b) {
             const float2* Gb = Gt + (int64_t)b * strideG;
             float2* Sb = S + (int64_t)b * strideS;
             float2 gh[VPT];
@@ -780,31 +791,62 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint_items(
     }
 }
 
+// dR[i] = (accumulate ? dR[i] : 0) + sum_g part[g * stride + i], i < n, in group order.
+__global__ __launch_bounds__(256) void k_sum_parts(float2* __restrict__ dR, const float2* __restrict__ part,
+                                                   int64_t stride, int groups, int64_t n, int accumulate) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        float2 a = accumulate ? dR[i] : make_float2(0.f, 0.f);
+        for (int g = 0; g < groups; ++g) {
+            const float2 v = part[(int64_t)g * stride + i];
+            a.x += v.x;
+            a.y += v.y;
+        }
+        dR[i] = a;
+    }
+}
+
+int wire_adjoint_groups(int batch, size_t scratch_bytes, int n_imp, int nw_fft, int nt_fft) {
+    const size_t one = (size_t)n_imp * nw_fft * (nt_fft / 2 + 1) * sizeof(float2);
+    int g = batch < kAdjointGroups ? batch : kAdjointGroups;
+    while (g > 1 && (size_t)g * one > scratch_bytes) --g;
+    return g < 1 ? 1 : g;
+}
+
 hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS,
                                      int64_t strideS, int batch, int n_wires, int n_imp, int nw_fft,
                                      int nt_fft, const float2* R, float2* dR, float resp_scale,
-                                     hipStream_t s, bool accumulate) {
+                                     hipStream_t s, bool accumulate, void* scratch, size_t scratch_bytes) {
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     if (batch <= 0) return hipSuccess;
     const int F = nt_fft / 2 + 1, nyq = nt_fft / 2;
+    const int groups = dR ? wire_adjoint_groups(batch, scratch ? scratch_bytes : 0, n_imp, nw_fft, nt_fft)
+                          : (batch < kAdjointGroups ? batch : kAdjointGroups);
+    const int64_t pstride = (int64_t)n_imp * nw_fft * F;
+    float2* part = reinterpret_cast<float2*>(scratch);
     constexpr int C = 8;
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
-    dim3 grid((F + C - 1) / C);
+    dim3 grid((unsigned)(((F + C - 1) / C) * groups));
+    hipError_t e = hipErrorInvalidValue;
 #define LAR_WADJI(V, NT)                                                                                \
     {                                                                                                   \
         set_lds(k_wire_adjoint_items<V, C, NT>, lds);                                                   \
         hipLaunchKernelGGL((k_wire_adjoint_items<V, C, NT>), grid, dim3(NT), lds, s, Gt, ldG, strideG, S, \
-                           ldS, strideS, batch, n_wires, n_imp, F, nyq, plan, R, dR, resp_scale,        \
-                           accumulate ? 1 : 0);                                                         \
-        return hipGetLastError();                                                                       \
+                           ldS, strideS, batch, groups, n_wires, n_imp, F, nyq, plan, R, dR, part,      \
+                           pstride, resp_scale, accumulate ? 1 : 0);                                    \
+        e = hipGetLastError();                                                                          \
     }
     if (nw_fft <= 128) LAR_WADJI(2, 512)
-    if (nw_fft <= 256) LAR_WADJI(4, 512)
-    if (nw_fft <= 512) LAR_WADJI(8, 512)
-    if (nw_fft <= 1024) LAR_WADJI(8, 1024)
+    else if (nw_fft <= 256) LAR_WADJI(4, 512)
+    else if (nw_fft <= 512) LAR_WADJI(8, 512)
+    else if (nw_fft <= 1024) LAR_WADJI(8, 1024)
 #undef LAR_WADJI
-    return hipErrorInvalidValue;
+    if (e != hipSuccess || !dR || groups == 1) return e;
+    const int64_t b = (pstride + 255) / 256, cap = 8 * (int64_t)device_cus();
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(b < cap ? b : cap)), dim3(256), 0, s, dR, part, pstride, groups,
+                       pstride, accumulate ? 1 : 0);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- response spectrum

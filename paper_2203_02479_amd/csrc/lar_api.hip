@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <vector>
 
 #include "lar_internal.hpp"
 
@@ -275,19 +276,11 @@ int lar_sim_plane_workspace(const lar_plane* plane, int64_t n_depos, const lar_f
     return LAR_OK;
 }
 
-int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
-                  const lar_fluct* fluct, const float* resp, float* wave, void* ws,
-                  size_t ws_bytes, void* stream) {
+// lar_sim_plane after its argument checks
+static int sim_plane_impl(const lar_plane* plane, const lar_depos* depos, float nsigma, const lar_fluct* fluct,
+                          const float* resp, float* wave, void* ws, size_t ws_bytes, hipStream_t s) {
     int st;
-    if ((st = check_fft(plane))) return st;
-    if ((st = check_depos(depos))) return st;
-    if ((st = check_fluct(fluct, plane))) return st;
-    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
-    if (!resp || !wave) return LAR_EINVAL;
     const size_t head = grid_bytes(plane) + fftconv_bytes(plane);
-    const size_t need = head + raster_bytes_min(depos->n, fluct);
-    if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
     char* w = reinterpret_cast<char*>(ws);
     float* grid = reinterpret_cast<float*>(w);
     LAR_TRY(launch_fill(grid, (int64_t)plane->n_wires * plane->n_imp * plane->n_ticks, s));
@@ -300,6 +293,134 @@ int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
         LAR_TRY(stage_mark(2, s));
     }
     return fftconv_impl(plane, grid, resp, wave, w + grid_bytes(plane), s);
+}
+
+int lar_sim_plane(const lar_plane* plane, const lar_depos* depos, float nsigma,
+                  const lar_fluct* fluct, const float* resp, float* wave, void* ws,
+                  size_t ws_bytes, void* stream) {
+    int st;
+    if ((st = check_fft(plane))) return st;
+    if ((st = check_depos(depos))) return st;
+    if ((st = check_fluct(fluct, plane))) return st;
+    if (!(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    if (!resp || !wave) return LAR_EINVAL;
+    const size_t need = grid_bytes(plane) + fftconv_bytes(plane) + raster_bytes_min(depos->n, fluct);
+    if (!ws || ws_bytes < need || reinterpret_cast<uintptr_t>(ws) % 256) return LAR_EWORKSPACE;
+    return sim_plane_impl(plane, depos, nsigma, fluct, resp, wave, ws, ws_bytes, (hipStream_t)stream);
+}
+
+// ---- independent plane simulations on several streams (the single-GPU
+// form of the paper's several processes per GPU, Sec. 3.3)
+
+// Events of this host thread's calls, created on first use and kept: a
+// stream wait takes the event's record made before the wait, so recording
+// the same event again in a later call leaves earlier waits unchanged.
+static thread_local std::vector<hipEvent_t> g_stream_ev;
+
+static int stream_events(int n, hipEvent_t** out) {
+    while ((int)g_stream_ev.size() < n) {
+        hipEvent_t e = nullptr;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return hip_status(r);
+        g_stream_ev.push_back(e);
+    }
+    *out = g_stream_ev.data();
+    return LAR_OK;
+}
+
+// workspace slice of one stream: the largest lar_sim_plane workspace of the items
+static size_t streams_slice(const lar_plane* planes, int32_t n_types, const lar_batch_item* items, int32_t n_items,
+                            const lar_fluct* fluct) {
+    size_t m = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const lar_plane* p = &planes[items[i].plane_type];
+        const size_t b = grid_bytes(p) + fftconv_bytes(p) + raster_bytes(items[i].n_depos, fluct);
+        m = b > m ? b : m;
+    }
+    (void)n_types;
+    return align_up(m, 256);
+}
+
+static int streams_check(const lar_plane* planes, int32_t n_types, const lar_batch_item* items, int32_t n_items,
+                         const lar_fluct* fluct, int32_t n_streams) {
+    int st;
+    if (!planes || n_types < 1 || !items || n_items < 0 || n_streams < 1 || n_streams > 64) return LAR_EINVAL;
+    for (int t = 0; t < n_types; ++t) {
+        if ((st = check_fft(&planes[t]))) return st;
+        if ((st = check_fluct(fluct, &planes[t]))) return st;
+    }
+    for (int i = 0; i < n_items; ++i) {
+        const lar_batch_item& it = items[i];
+        if (it.plane_type < 0 || it.plane_type >= n_types || it.n_depos < 0 || it.depo_offset < 0 ||
+            it.wave_offset < 0 || it.plane >= 256u)
+            return LAR_EINVAL;
+        if (it.n_depos > (int64_t)UINT32_MAX) return LAR_ESIZE;
+    }
+    return LAR_OK;
+}
+
+int lar_sim_streams_workspace(const lar_plane* planes, int32_t n_types, const lar_batch_item* items,
+                              int32_t n_items, const lar_fluct* fluct, int32_t n_streams, size_t* bytes) {
+    int st;
+    if ((st = streams_check(planes, n_types, items, n_items, fluct, n_streams))) return st;
+    if (!bytes) return LAR_EINVAL;
+    *bytes = streams_slice(planes, n_types, items, n_items, fluct) * (size_t)n_streams;
+    return LAR_OK;
+}
+
+int lar_sim_streams(const lar_plane* planes, int32_t n_types, const float* const* resp, const lar_depos* depos,
+                    float nsigma, const lar_fluct* fluct, const lar_batch_item* items, int32_t n_items,
+                    float* wave, void* const* streams, int32_t n_streams, void* ws, size_t ws_bytes,
+                    void* stream) {
+    int st;
+    if ((st = streams_check(planes, n_types, items, n_items, fluct, n_streams))) return st;
+    if (!resp || !depos || !wave || !streams || !(nsigma > 0.f) || !isfinite(nsigma)) return LAR_EINVAL;
+    for (int i = 0; i < n_streams; ++i)
+        if (!streams[i] || streams[i] == stream) return LAR_EINVAL;
+    for (int i = 0; i < n_items; ++i) {
+        if (!resp[items[i].plane_type]) return LAR_EINVAL;
+        if (items[i].depo_offset + items[i].n_depos > depos->n) return LAR_EINVAL;
+    }
+    if (depos->n > 0 && (!depos->q || !depos->t || !depos->x || !depos->sigma_t || !depos->sigma_x))
+        return LAR_EINVAL;
+    const size_t slice = streams_slice(planes, n_types, items, n_items, fluct);
+    if (!ws || ws_bytes < slice * (size_t)n_streams || reinterpret_cast<uintptr_t>(ws) % 256)
+        return LAR_EWORKSPACE;
+    if (n_items == 0) return LAR_OK;
+    hipEvent_t* ev = nullptr;
+    if ((st = stream_events(n_streams + 1, &ev))) return st;
+    hipStream_t main = (hipStream_t)stream;
+    // fork: every worker stream starts after the work already on `stream`
+    LAR_TRY(hipEventRecord(ev[0], main));
+    const int used = n_items < n_streams ? n_items : n_streams;
+    for (int i = 0; i < used; ++i) LAR_TRY(hipStreamWaitEvent((hipStream_t)streams[i], ev[0], 0));
+    for (int i = 0; i < n_items; ++i) {
+        const lar_batch_item& it = items[i];
+        const int si = i % n_streams;
+        lar_depos d;
+        d.n = it.n_depos;
+        d.q = depos->q + it.depo_offset;
+        d.t = depos->t + it.depo_offset;
+        d.x = depos->x + it.depo_offset;
+        d.sigma_t = depos->sigma_t + it.depo_offset;
+        d.sigma_x = depos->sigma_x + it.depo_offset;
+        lar_fluct f{};
+        if (fluct) {
+            f = *fluct;
+            f.event = it.event;
+            f.plane = it.plane;
+        }
+        if ((st = sim_plane_impl(&planes[it.plane_type], &d, nsigma, fluct ? &f : nullptr, resp[it.plane_type],
+                                 wave + it.wave_offset, reinterpret_cast<char*>(ws) + slice * si, slice,
+                                 (hipStream_t)streams[si])))
+            return st;
+    }
+    // join: `stream` continues after every worker stream's work
+    for (int i = 0; i < used; ++i) {
+        LAR_TRY(hipEventRecord(ev[1 + i], (hipStream_t)streams[i]));
+        LAR_TRY(hipStreamWaitEvent(main, ev[1 + i], 0));
+    }
+    return LAR_OK;
 }
 
 // fftconv backward workspace: [FT of wave_grad rows: N_w x ld][grid rows: R_rows x ld]

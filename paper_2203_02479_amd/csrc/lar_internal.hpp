@@ -338,11 +338,16 @@ hipError_t launch_digitize(const float* wave, const float* noise, int64_t n, flo
                            int bits, uint16_t* out, hipStream_t s);
 // Adjoint wire pass over `batch` items sharing R (item b at Gt + b*strideG,
 // S + b*strideS): grid-gradient spectra written over S; dR = (or +=, with
-// accumulate) the gradient summed over the items.
+// accumulate) the gradient summed over the items.  The items are split in
+// up to kAdjointGroups groups of blocks, as many as whole response-gradient
+// partials fit in `scratch` (scratch_bytes; may be NULL: one group).
+constexpr int kAdjointGroups = 4;
+int wire_adjoint_groups(int batch, size_t scratch_bytes, int n_imp, int nw_fft, int nt_fft);
 hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t strideG, float2* S, int64_t ldS,
                                      int64_t strideS, int batch, int n_wires, int n_imp, int nw_fft,
                                      int nt_fft, const float2* R, float2* dR, float resp_scale,
-                                     hipStream_t s, bool accumulate);
+                                     hipStream_t s, bool accumulate, void* scratch = nullptr,
+                                     size_t scratch_bytes = 0);
 hipError_t launch_sample_counts(int mode, int64_t n, const float* q, const double* p,
                                 const uint32_t* ctr3, uint32_t plane, uint64_t seed, float* out,
                                 hipStream_t s);

@@ -102,6 +102,11 @@ SIGNATURES = {
     "lar_batch_waves": ([_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
     "lar_batch_backward": ([_VP, _VP, _P(_VP), _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "lar_batch_run": ([_VP, _VP], ctypes.c_int),
+    "lar_sim_streams_workspace": ([_P(lar_plane), ctypes.c_int32, _P(lar_batch_item), ctypes.c_int32,
+                                   _P(lar_fluct), ctypes.c_int32, _P(_SZ)], ctypes.c_int),
+    "lar_sim_streams": ([_P(lar_plane), ctypes.c_int32, _P(_VP), _P(lar_depos), ctypes.c_float, _P(lar_fluct),
+                         _P(lar_batch_item), ctypes.c_int32, _VP, _P(_VP), ctypes.c_int32, _VP, _SZ, _VP],
+                        ctypes.c_int),
     "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
@@ -499,3 +504,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- streams
+
+def sim_streams_workspace(planes, items, fluct, n_streams) -> int:
+    pls = (lar_plane * len(planes))(*[make_plane(p) for p in planes])
+    its = make_items(items)
+    n = ctypes.c_size_t(0)
+    _check(_lib().lar_sim_streams_workspace(pls, len(planes), its, len(its), _fluct(fluct), int(n_streams),
+                                            ctypes.byref(n)), "lar_sim_streams_workspace")
+    return n.value
+
+
+def sim_streams(planes, resps, depos: DeviceDepos, nsigma, fluct, items, wave, streams, ws, stream=None):
+    """Items as independent lar_sim_plane calls spread over `streams`
+    (torch.cuda.Stream objects, default priority), joined back to `stream`."""
+    pls = (lar_plane * len(planes))(*[make_plane(p) for p in planes])
+    rp = (ctypes.c_void_p * len(resps))(*[r.data_ptr() for r in resps])
+    its = make_items(items)
+    ds = depos.struct()
+    sp = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
+    _check(_lib().lar_sim_streams(pls, len(planes), rp, ctypes.byref(ds), float(nsigma), _fluct(fluct), its, len(its),
+                                  _ptr(wave), sp, len(streams), _ptr(ws), ws.numel(), _stream(stream)),
+           "lar_sim_streams")

@@ -98,6 +98,32 @@ def test_host_side_argument_errors(lar):
     assert L.lar_sample_counts(1, 0, None, None, None, 0, 0, None, None) == lar.LAR_OK
 
 
+def test_streams_host_side_errors(lar):
+    L = lar.lib()
+    P = lar.make_plane(inputs.cfg0_plane())
+    pls = (lar.lar_plane * 1)(P)
+    its = lar.make_items([(0, 0, 0, 0, 10, 0)])
+    one = ctypes.c_void_p(256)
+    nb = ctypes.c_size_t(0)
+    assert L.lar_sim_streams_workspace(pls, 1, its, 1, None, 0, ctypes.byref(nb)) == lar.LAR_EINVAL
+    assert L.lar_sim_streams_workspace(pls, 1, its, 1, None, 65, ctypes.byref(nb)) == lar.LAR_EINVAL
+    assert L.lar_sim_streams_workspace(pls, 1, its, 1, None, 3, ctypes.byref(nb)) == lar.LAR_OK
+    assert nb.value == 3 * lar.sim_plane_workspace(inputs.cfg0_plane(), 10, None)
+    bad = lar.make_items([(1, 0, 0, 0, 10, 0)])
+    assert L.lar_sim_streams_workspace(pls, 1, bad, 1, None, 3, ctypes.byref(nb)) == lar.LAR_EINVAL
+    rp = (ctypes.c_void_p * 1)(256)
+    d = lar.lar_depos(one, one, one, one, one, 10)
+    st = (ctypes.c_void_p * 2)(512, 512 + 64)
+    # a worker stream equal to the caller's stream, a missing workspace
+    assert L.lar_sim_streams(pls, 1, rp, ctypes.byref(d), 3.0, None, its, 1, one, st, 2, one, 1 << 30,
+                             ctypes.c_void_p(512)) == lar.LAR_EINVAL
+    assert L.lar_sim_streams(pls, 1, rp, ctypes.byref(d), 3.0, None, its, 1, one, st, 2, None, 0,
+                             None) == lar.LAR_EWORKSPACE
+    d = lar.lar_depos(one, one, one, one, one, 5)     # item reaches past the depos
+    assert L.lar_sim_streams(pls, 1, rp, ctypes.byref(d), 3.0, None, its, 1, one, st, 2, one, 1 << 30,
+                             None) == lar.LAR_EINVAL
+
+
 def test_stage_calls_host_side_errors(lar):
     L = lar.lib()
     one = ctypes.c_void_p(256)

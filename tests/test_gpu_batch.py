@@ -228,14 +228,21 @@ def test_batch_backward_vs_oracle():
     b = lar.Batch(planes, resps, D, inputs.NSIGMA, None, items, wave, ws)
     assert b.waves() == (3, 2)
     G = np.random.default_rng(5).standard_normal(total).astype(np.float32)
-    rg = [torch.full_like(r, float("nan")) for r in resps]
-    dg = [torch.full((len(cat),), float("nan"), device="cuda") for _ in range(5)]
-    b.backward(torch.as_tensor(G).cuda(), rg, dg)
-    torch.cuda.synchronize()
+    Gd = torch.as_tensor(G).cuda()
+    runs = []
+    # without a forward run every wave is recomputed; right after a run the
+    # last wave's spectra are reused
+    for with_run in (False, True):
+        rg = [torch.full_like(r, float("nan")) for r in resps]
+        dg = [torch.full((len(cat),), float("nan"), device="cuda") for _ in range(5)]
+        if with_run:
+            b.run()
+        b.backward(Gd, rg, dg)
+        torch.cuda.synchronize()
+        runs.append(([r.cpu().numpy().astype(np.float64) for r in rg], [d.cpu().numpy() for d in dg]))
     b.close()
     Rc = [oracle.response_spectrum(p, r) for p, r in zip(planes, rtime)]
     dR_ref = [np.zeros_like(R) for R in Rc]
-    dg_np = [d.cpu().numpy() for d in dg]
     for (pt, e, pl, off, n, wo), d in zip(items, chunks):
         P = planes[pt]
         d = d.take(slice(0, n))
@@ -246,8 +253,61 @@ def test_batch_backward_vs_oracle():
         if n == 0:
             continue
         ref = oracle.raster_adjoint(P, d, inputs.NSIGMA, GS)
-        for k, name in enumerate(("q", "t", "x", "sigma_t", "sigma_x")):
-            assert rel_l2(dg_np[k][off:off + n], ref[k]) < 1e-4, (e, pl, name)
-    for t in range(2):
-        got = rg[t].cpu().numpy().astype(np.float64)
-        assert rel_l2(got[..., 0] + 1j * got[..., 1], dR_ref[t]) < 1e-4, t
+        for rg_np, dg_np in runs:
+            for k, name in enumerate(("q", "t", "x", "sigma_t", "sigma_x")):
+                assert rel_l2(dg_np[k][off:off + n], ref[k]) < 1e-4, (e, pl, name)
+    for rg_np, _ in runs:
+        for t in range(2):
+            got = rg_np[t]
+            assert rel_l2(got[..., 0] + 1j * got[..., 1], dR_ref[t]) < 1e-4, t
+
+
+# ------------------------------------------------------------------ concurrent streams
+
+@pytest.mark.parametrize("mode,n_streams", [(1, 3), (0, 2), (3, 4), (1, 1)])
+def test_streams_match_single_plane_runs(mode, n_streams):
+    """Items spread over several streams give the per-item lar_sim_plane
+    waveforms (fluctuated counts exactly), ordered after earlier work on the
+    caller's stream and before later work."""
+    torch, lar, planes, resps, items, deps, cat, fl, total = _setup(fluct_mode=mode)
+    D = lar.DeviceDepos.from_host(cat)
+    ref = _reference(torch, lar, planes, resps, items, deps, fl, total)
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    ws = lar.workspace(lar.sim_streams_workspace(planes, items, fl, n_streams))
+    wave = torch.empty(total, device="cuda")
+    for rep in range(3):
+        wave.fill_(-7.0)                              # earlier work on the caller's stream
+        lar.sim_streams(planes, resps, D, 3.0, fl, items, wave, streams, ws)
+        snap = wave.clone()                           # later work on the caller's stream
+        torch.cuda.synchronize()
+        got = snap.cpu().numpy()
+        gaps = np.ones(total, bool)
+        for (pt, e, pl, off, n, wo) in items:
+            gaps[wo:wo + planes[pt].n_wires * planes[pt].n_ticks] = False
+        assert np.all(got[gaps] == -7.0)
+        if mode:
+            assert np.array_equal(got[~gaps], ref[~gaps]), rep
+        else:
+            np.testing.assert_allclose(got[~gaps], ref[~gaps], rtol=0, atol=1e-5 * np.abs(ref).max())
+
+
+def test_streams_three_planes_vs_oracle():
+    """Two events of the three-plane geometry on four streams, mean path:
+    each item against the oracle (relative L2 1e-5, max |diff| 1e-5 of max
+    |ref|)."""
+    torch, lar, planes, rtime, resps, items, chunks, cat, total = _three_plane_batch(2, 30_000, 1_500,
+                                                                                    inputs.SEED0 + 800)
+    D = lar.DeviceDepos.from_host(cat)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    ws = lar.workspace(lar.sim_streams_workspace(planes, items, None, 4))
+    wave = torch.full((total,), float("nan"), device="cuda")
+    lar.sim_streams(planes, resps, D, inputs.NSIGMA, None, items, wave, streams, ws)
+    torch.cuda.synchronize()
+    got_all = wave.cpu().numpy()
+    Rc = [oracle.response_spectrum(p, r) for p, r in zip(planes, rtime)]
+    for (pt, e, pl, off, n, wo), d in zip(items, chunks):
+        P = planes[pt]
+        got = got_all[wo:wo + P.n_wires * P.n_ticks].reshape(P.n_wires, P.n_ticks)
+        ref = oracle.sim_plane_mean(P, d, Rc[pt])
+        assert rel_l2(got, ref) < 1e-5, (e, pl)
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), (e, pl)
