@@ -394,10 +394,11 @@ int lar_sim_streams(const lar_plane *planes, int32_t n_types, const float *const
  * computes the same transform up to float rounding; which one is fastest
  * depends on the shape.  Schedules are keyed by (n_wires, n_imp, n_ticks,
  * nt_fft, nw_fft), process-wide, and read when a call launches its kernels
- * (lar_batch_create reads them once).  Radix orders 0..3 pick the order of
- * the radix-8/4/3/2 passes of a transform:
+ * (lar_batch_create reads them once).  Radix orders 0..4 pick the order of
+ * the radix-8/6/4/3/2 passes of a transform:
  *   0: 8s (then one 4 or 2), then 3s   1: 4s, 3s, then one 2
- *   2: 3s, then 8s (then one 4 or 2)  3: the reverse of 0 */
+ *   2: 3s, then 8s (then one 4 or 2)  3: the reverse of 0
+ *   4: 8s, then each remaining 2 paired with a 3 as a 6, then the rest */
 typedef struct lar_schedule {
     int32_t row_threads;    /* threads per time-axis row workgroup: 256, 384, 512, 768, 1024 */
     int32_t row_order;      /* radix order of the nt_fft/2-point plan */

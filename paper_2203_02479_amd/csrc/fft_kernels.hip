@@ -12,6 +12,10 @@
 //
 // All three are bound by HBM traffic: every transform lives in LDS and each
 // grid element is read and written once per pass.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "lar_internal.hpp"
 
 namespace lar {
@@ -33,6 +37,13 @@ bool make_plan(int n, FftPlan* plan, int order) {
     if (order == 0 || order == 3) {
         twos_8();
         threes();
+    } else if (order == 4) {
+        int x = a, y = b;
+        while (x >= 3) { r[np++] = 8; x -= 3; }
+        while (x > 0 && y > 0) { r[np++] = 6; --x; --y; }
+        if (x == 2) r[np++] = 4;
+        if (x == 1) r[np++] = 2;
+        for (int i = 0; i < y; ++i) r[np++] = 3;
     } else if (order == 1) {
         int x = a;
         while (x >= 2) { r[np++] = 4; x -= 2; }
@@ -119,7 +130,63 @@ __device__ __forceinline__ float2 row_pair(float2 raw, int n, int n_in) {
     return make_float2(2 * n < n_in ? raw.x : 0.f, 2 * n + 1 < n_in ? raw.y : 0.f);
 }
 
-template <int VPT, int NT>
+// LDS of the row kernels: the padded transform buffer, the half-angle
+// table h and, with PM, the pass-major twiddle tables.
+static size_t row_lds_bytes(const FftPlan& plan, bool pm) {
+    return ((size_t)lds_slots(plan.n, 1) + plan.n + (pm ? pm_entries(plan) : 0)) * sizeof(float2);
+}
+
+// Row transform with the twiddles of the half table (TwHalf) or of the
+// pass-major tables (PM); p0 = 1 when the first pass ran in registers.
+template <int VPT, int PM>
+__device__ __forceinline__ void row_fft(float2* A, const FftPlan& plan, int tid, int T, const float2* h,
+                                        const float2* tp, bool inv, int p0) {
+    if (PM) {
+        fft_lds_pm<VPT, 1, 1>(A, plan, tid, T, tp, inv, p0);
+    } else {
+        // (p0 is 0 here: the register first pass is used with PM only)
+        const TwHalf tw{h, plan.n};
+        int Ns = 1;
+        for (int p = 0; p < plan.npass; ++p) {
+            const int R = plan.radix[p];
+            if (R == 8) stockham_pass_tw<8, (VPT + 7) / 8>(A, plan.n, Ns, tid, T, tw, inv);
+            else if (R == 6) stockham_pass_tw<6, (VPT + 5) / 6>(A, plan.n, Ns, tid, T, tw, inv);
+            else if (R == 4) stockham_pass_tw<4, (VPT + 3) / 4>(A, plan.n, Ns, tid, T, tw, inv);
+            else if (R == 3) stockham_pass_tw<3, (VPT + 2) / 3>(A, plan.n, Ns, tid, T, tw, inv);
+            else stockham_pass_tw<2, (VPT + 1) / 2>(A, plan.n, Ns, tid, T, tw, inv);
+            Ns *= R;
+        }
+    }
+}
+
+// Split step of the real FFT from the Tf/2-point complex transform Z in A:
+// X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2, W = exp(-2 pi i / Tf),
+// written for k <= Nh/2 and Nh - k.
+__device__ __forceinline__ void r2c_split(const float2* A, const float2* h, int Nh, int tid, int T,
+                                          float2* __restrict__ y) {
+    for (int k = tid; k <= Nh / 2; k += T) {
+        float2 zk = A[lidx<1>(k)], zm = A[lidx<1>(k == 0 ? 0 : Nh - k)];
+        float2 w = h[k];
+        float2 e1 = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        float2 d1 = make_float2(zk.x - zm.x, zk.y + zm.y);
+        float2 wd1 = cmul(w, d1);
+        float2 xk = make_float2(e1.x + 0.5f * wd1.y, e1.y - 0.5f * wd1.x);
+        float2 e2 = make_float2(0.5f * (zm.x + zk.x), 0.5f * (zm.y - zk.y));
+        float2 d2 = make_float2(zm.x - zk.x, zm.y + zk.y);
+        float2 wd2 = cmul(make_float2(-w.x, w.y), d2);    // W^(Nh-k) = -conj(W^k)
+        float2 xm = make_float2(e2.x + 0.5f * wd2.y, e2.y - 0.5f * wd2.x);
+        y[k] = xk;
+        y[Nh - k] = xm;
+    }
+}
+
+// Time-axis real FFT of rows: Tf real samples (n_in read, the rest zero)
+// as a Tf/2-point complex FFT of even/odd pairs, then the split step.  A
+// persistent workgroup loops over rows and loads the next row while the
+// current one is transformed.  When every thread holds exactly the inputs
+// of one first-pass butterfly (VPT = first radix, NT * VPT = Tf/2) that
+// pass runs in registers straight from the loads.
+template <int VPT, int NT, int PM, int REG>
 __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
                                                           int64_t ld_in, int n_in, int nrows,
                                                           FftPlan plan, float2* __restrict__ out,
@@ -128,42 +195,62 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
-    float2* h = lds + Nh;
+    float2* h = lds + lds_slots(Nh, 1);
+    float2* tp = h + Nh;
     fill_half_table(h, Nh, tid, T);
-    const TwHalf tw{h, Nh};
+    if (PM) {
+        lds_barrier();
+        build_pm(tp, plan, TwHalf{h, Nh}, tid, T);
+    }
+    // REG (chosen by the launcher): plan.radix[0] == VPT, NT * VPT == Nh,
+    // and rows of even length at 8-byte aligned starts (pairs_ok)
+    constexpr bool kReg = REG && (VPT == 2 || VPT == 4 || VPT == 8);
     float2 v[VPT];
     // input row r starts at row_in[r] when given, else at r * ld_in
     auto row_ptr = [&](int r) { return in + (row_in ? row_in[r] : (int64_t)r * ld_in); };
     int row = blockIdx.x;
+    if constexpr (kReg) {
+        // lean loop: one 8-byte load per pair, the pair masked as a whole
+        const int last = (n_in >> 1) - 1;
+        auto issue = [&](int r) {
+            const float2* x2 = reinterpret_cast<const float2*>(row_ptr(r));
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) v[i] = x2[min(tid + i * T, last)];
+        };
+        if (row < nrows) issue(row);
+        for (; row < nrows; row += gridDim.x) {
+            lds_barrier();
+            // thread tid holds z[tid + r T], the inputs of butterfly tid of the
+            // first pass (Ns = 1: no twiddles); its outputs go to tid * VPT + r
+            float2 u[VPT];
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) u[i] = 2 * (tid + i * T) < n_in ? v[i] : make_float2(0.f, 0.f);
+            if (row + (int)gridDim.x < nrows) issue(row + gridDim.x);
+            dft_small<VPT>(u, false);
+#pragma unroll
+            for (int r = 0; r < VPT; ++r) A[lidx<1>(tid * VPT + r)] = u[r];
+            lds_barrier();
+            row_fft<VPT, PM>(A, plan, tid, T, h, tp, false, 1);
+            r2c_split(A, h, Nh, tid, T, out + (int64_t)row * ld_out);
+        }
+        return;
+    }
     if (row < nrows) issue_row_pairs<VPT>(row_ptr(row), n_in, tid, T, pairs_ok != 0, v);
     for (; row < nrows; row += gridDim.x) {
         lds_barrier();
+        {
 #pragma unroll
-        for (int i = 0; i < VPT; ++i) {
-            int n = tid + i * T;
-            if (n < Nh) A[n] = row_pair(v[i], n, n_in);
+            for (int i = 0; i < VPT; ++i) {
+                int n = tid + i * T;
+                if (n < Nh) A[lidx<1>(n)] = row_pair(v[i], n, n_in);
+            }
+            // prefetch the next row of this workgroup while this one is transformed
+            if (row + (int)gridDim.x < nrows)
+                issue_row_pairs<VPT>(row_ptr(row + gridDim.x), n_in, tid, T, pairs_ok != 0, v);
+            lds_barrier();
+            row_fft<VPT, PM>(A, plan, tid, T, h, tp, false, 0);
         }
-        // prefetch the next row of this workgroup while this one is transformed
-        if (row + (int)gridDim.x < nrows)
-            issue_row_pairs<VPT>(row_ptr(row + gridDim.x), n_in, tid, T, pairs_ok != 0, v);
-        lds_barrier();
-        fft_lds<VPT, 1>(A, plan, tid, T, tw, false);
-        // split step: X[k] = (Z[k] + Z*[Nh-k])/2 - i W^k (Z[k] - Z*[Nh-k])/2
-        float2* y = out + (int64_t)row * ld_out;
-        for (int k = tid; k <= Nh / 2; k += T) {
-            float2 zk = A[k], zm = A[k == 0 ? 0 : Nh - k];
-            float2 w = h[k];
-            float2 e1 = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            float2 d1 = make_float2(zk.x - zm.x, zk.y + zm.y);
-            float2 wd1 = cmul(w, d1);
-            float2 xk = make_float2(e1.x + 0.5f * wd1.y, e1.y - 0.5f * wd1.x);
-            float2 e2 = make_float2(0.5f * (zm.x + zk.x), 0.5f * (zm.y - zk.y));
-            float2 d2 = make_float2(zm.x - zk.x, zm.y + zk.y);
-            float2 wd2 = cmul(make_float2(-w.x, w.y), d2);    // W^(Nh-k) = -conj(W^k)
-            float2 xm = make_float2(e2.x + 0.5f * wd2.y, e2.y - 0.5f * wd2.x);
-            y[k] = xk;
-            y[Nh - k] = xm;
-        }
+        r2c_split(A, h, Nh, tid, T, out + (int64_t)row * ld_out);
     }
 }
 
@@ -179,7 +266,7 @@ __device__ __forceinline__ void load_spec_pairs(const float2* __restrict__ X, in
     }
 }
 
-template <int VPT, int NT>
+template <int VPT, int NT, int PM>
 __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                                                           int64_t ld_in, int nrows, FftPlan plan,
                                                           float* __restrict__ out, int64_t ld_out,
@@ -188,9 +275,13 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
     extern __shared__ float2 lds[];
     const int Nh = plan.n, tid = threadIdx.x, T = NT;
     float2* A = lds;
-    float2* h = lds + Nh;
+    float2* h = lds + lds_slots(Nh, 1);
+    float2* tp = h + Nh;
     fill_half_table(h, Nh, tid, T);
-    const TwHalf tw{h, Nh};
+    if (PM) {
+        lds_barrier();
+        build_pm(tp, plan, TwHalf{h, Nh}, tid, T);
+    }
     // the pre-step touches Nh/2 + 1 bin pairs: VPT/2 (rounded up) per thread
     constexpr int VH = (VPT + 1) / 2 + 1;
     float2 xa[VH], xb[VH];
@@ -211,26 +302,26 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                 float2 b1 = cmulc(make_float2(xk.x - xm.x, xk.y + xm.y), w);   // * exp(+2 pi i k/Tf)
                 float2 a2 = make_float2(xm.x + xk.x, xm.y - xk.y);
                 float2 b2 = cmul(make_float2(xm.x - xk.x, xm.y + xk.y), make_float2(-w.x, -w.y));
-                A[k] = make_float2(a1.x - b1.y, a1.y + b1.x);
-                if (k > 0) A[Nh - k] = make_float2(a2.x - b2.y, a2.y + b2.x);
+                A[lidx<1>(k)] = make_float2(a1.x - b1.y, a1.y + b1.x);
+                if (k > 0) A[lidx<1>(Nh - k)] = make_float2(a2.x - b2.y, a2.y + b2.x);
             }
         }
         if (row + (int)gridDim.x < nrows)
             load_spec_pairs<VH>(in + (int64_t)(row + gridDim.x) * ld_in, Nh, tid, T, xa, xb);
         lds_barrier();
-        fft_lds<VPT, 1>(A, plan, tid, T, tw, true);
+        row_fft<VPT, PM>(A, plan, tid, T, h, tp, true, 0);
         float* y = out + (row_off ? row_off[row] : (int64_t)row * ld_out);
         if (pairs_ok) {
             float2* y2 = reinterpret_cast<float2*>(y);
             const int full = n_out >> 1;
             for (int n = tid; n < Nh; n += T) {
-                float2 z = A[n];
+                float2 z = A[lidx<1>(n)];
                 if (n < full) y2[n] = make_float2(z.x * scale, z.y * scale);
                 else if (2 * n < n_out) y[2 * n] = z.x * scale;
             }
         } else {
             for (int n = tid; n < Nh; n += T) {
-                float2 z = A[n];
+                float2 z = A[lidx<1>(n)];
                 if (2 * n < n_out) y[2 * n] = z.x * scale;
                 if (2 * n + 1 < n_out) y[2 * n + 1] = z.y * scale;
             }
@@ -238,17 +329,59 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
     }
 }
 
+// Per-kernel launch facts cached on the host: the dynamic LDS limit set so
+// far and the resident workgroups per CU for a (threads, LDS) launch, so
+// that a launch makes no attribute or occupancy query once they are known.
+namespace {
+struct KernelFacts {
+    size_t lds_set = 65536;                  // larger sizes need the attribute
+    std::map<std::pair<int, size_t>, int> per_cu;
+};
+std::mutex g_facts_mu;
+std::map<std::pair<int, const void*>, KernelFacts> g_facts;   // (device, kernel)
+
+KernelFacts& facts(const void* k) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return g_facts[std::make_pair(dev, k)];
+}
+}  // namespace
+
 template <class K>
 static void set_lds(K kernel, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* k = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(g_facts_mu);
+    KernelFacts& f = facts(k);
+    if (bytes > f.lds_set &&
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        f.lds_set = bytes;
 }
 
-static int row_grid(int nrows) {
-    int g = 4 * device_cus();
+template <class K>
+static int blocks_per_cu(K kernel, int threads, size_t lds) {
+    const void* k = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(g_facts_mu);
+    KernelFacts& f = facts(k);
+    const auto key = std::make_pair(threads, lds);
+    auto it = f.per_cu.find(key);
+    if (it != f.per_cu.end()) return it->second;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, lds) != hipSuccess || per < 1) per = 1;
+    f.per_cu[key] = per;
+    return per;
+}
+
+// Persistent grid of a row kernel: as many workgroups as are resident at
+// once (occupancy from the kernel's registers and this launch's LDS), at
+// most one per row.
+template <class K>
+static int row_grid(K kernel, int threads, size_t lds, int nrows) {
+    const int g = blocks_per_cu(kernel, threads, lds) * device_cus();
     return nrows < g ? nrows : g;
 }
+
+// The pass-major tables fit next to the buffer and the half table.
+static bool row_pm(const FftPlan& plan) { return row_lds_bytes(plan, true) <= kLdsBytes; }
 
 // Values per thread of a transform of n points over T threads, rounded up to
 // the instantiated 1, 2, 4 or 8; 0 if more than 8 would be needed.
@@ -311,20 +444,28 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
     const int Nh = plan.n, vpt = vpt_for(Nh, threads);
     if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const size_t lds = 2 * (size_t)Nh * sizeof(float2);
+    const bool pm = row_pm(plan);
+    const size_t lds = row_lds_bytes(plan, pm);
     const int pairs_ok = ((ld_in % 2) == 0 && (n_in % 2) == 0 && (reinterpret_cast<uintptr_t>(in) % 8) == 0 &&
                           (row_in == nullptr || row_in_even))
                              ? 1
                              : 0;
-    dim3 grid(row_grid(nrows));
-#define LAR_R2C(V, T)                                                                           \
-    {                                                                                           \
-        set_lds(k_r2c_rows<V, T>, lds);                                                         \
-        hipLaunchKernelGGL((k_r2c_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, n_in, nrows,   \
-                           plan, out, ld_out, pairs_ok, row_in);                                \
+    // the first pass runs in registers when each thread holds one butterfly
+    const bool reg = pm && pairs_ok && plan.radix[0] == vpt && threads * vpt == Nh && vpt >= 2;
+#define LAR_R2C_PM(V, T, PM, RG)                                                                      \
+    {                                                                                                 \
+        set_lds(k_r2c_rows<V, T, PM, RG>, lds);                                                       \
+        dim3 grid(row_grid(k_r2c_rows<V, T, PM, RG>, T, lds, nrows));                                 \
+        hipLaunchKernelGGL((k_r2c_rows<V, T, PM, RG>), grid, dim3(T), lds, s, in, ld_in, n_in, nrows,  \
+                           plan, out, ld_out, pairs_ok, row_in);                                      \
     }
+#define LAR_R2C(V, T)                   \
+    if (reg) LAR_R2C_PM(V, T, 1, 1)     \
+    else if (pm) LAR_R2C_PM(V, T, 1, 0) \
+    else LAR_R2C_PM(V, T, 0, 0)
     LAR_ROW_DISPATCH(vpt, threads, LAR_R2C)
 #undef LAR_R2C
+#undef LAR_R2C_PM
     return hipGetLastError();
 }
 
@@ -337,20 +478,25 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
     const int Nh = plan.n, vpt = vpt_for(Nh, threads);
     if (!vpt) return hipErrorInvalidValue;
     if (nrows <= 0) return hipSuccess;
-    const size_t lds = 2 * (size_t)Nh * sizeof(float2);
+    const bool pm = row_pm(plan);
+    const size_t lds = row_lds_bytes(plan, pm);
     const int pairs_ok = ((ld_out % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 8) == 0 &&
                           (row_off == nullptr || row_off_even))
                              ? 1
                              : 0;
-    dim3 grid(row_grid(nrows));
-#define LAR_C2R(V, T)                                                                          \
-    {                                                                                          \
-        set_lds(k_c2r_rows<V, T>, lds);                                                        \
-        hipLaunchKernelGGL((k_c2r_rows<V, T>), grid, dim3(T), lds, s, in, ld_in, nrows, plan,  \
-                           out, ld_out, n_out, scale, pairs_ok, row_off);                      \
+#define LAR_C2R_PM(V, T, PM)                                                                    \
+    {                                                                                           \
+        set_lds(k_c2r_rows<V, T, PM>, lds);                                                     \
+        dim3 grid(row_grid(k_c2r_rows<V, T, PM>, T, lds, nrows));                               \
+        hipLaunchKernelGGL((k_c2r_rows<V, T, PM>), grid, dim3(T), lds, s, in, ld_in, nrows, plan, \
+                           out, ld_out, n_out, scale, pairs_ok, row_off);                       \
     }
+#define LAR_C2R(V, T)               \
+    if (pm) LAR_C2R_PM(V, T, 1)     \
+    else LAR_C2R_PM(V, T, 0)
     LAR_ROW_DISPATCH(vpt, threads, LAR_C2R)
 #undef LAR_C2R
+#undef LAR_C2R_PM
     return hipGetLastError();
 }
 
@@ -365,8 +511,65 @@ __device__ __forceinline__ void fill_full_table(float2* t, int n, int tid, int T
     }
 }
 
+// Pass-major twiddle tables of an n-point plan straight from FP64 sincospi
+// (rounded once), for kernels without a full table in LDS.
+__device__ __forceinline__ void build_pm_direct(float2* tp, const FftPlan& plan, int tid, int T) {
+    int Ns = 1, off = 0;
+    for (int p = 0; p < plan.npass; ++p) {
+        const int R = plan.radix[p], cnt = Ns * (R - 1), stride = plan.n / (Ns * R);
+        for (int e = tid; e < cnt; e += T) {
+            const int k = e / (R - 1), r = e - k * (R - 1) + 1;
+            double sn, cs;
+            sincospi(-2.0 * (double)(r * k * stride) / (double)plan.n, &sn, &cs);
+            tp[off + e] = make_float2((float)cs, (float)sn);
+        }
+        off += cnt;
+        Ns *= R;
+    }
+}
+
+// LDS of the wire pass: the padded [Wf][C] tile and the pass-major tables.
+static size_t wire_lds_bytes(const FftPlan& plan, int C) {
+    return ((size_t)lds_slots(plan.n * C, 1) + pm_entries(plan)) * sizeof(float2);
+}
+
+// First step of the transform of the [Wf][C] tile whose element
+// e = tid + i T the thread holds in x[i] (wire p = e / C, column e % C):
+// x goes to LDS, or, with REG (x holds the inputs of the thread's
+// first-pass butterfly: VPT = first radix, T / C = Wf / VPT), that pass runs
+// in registers and its outputs go to LDS.  x is dead afterwards; wire_fft_rest
+// finishes the transform in A.
+template <int VPT, int C, int REG>
+__device__ __forceinline__ void wire_fft_first(float2* A, int tid, int T, float2 (&x)[VPT], int nel, bool inv) {
+    if constexpr (REG != 0 && (VPT == 2 || VPT == 4 || VPT == 8)) {
+        dft_small<VPT>(x, inv);
+        const int j = tid / C, sc = tid % C;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) A[lidx<1>((j * VPT + r) * C + sc)] = x[r];
+    } else {
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int e = tid + i * T;
+            if (e < nel) A[lidx<1>(e)] = x[i];
+        }
+    }
+}
+template <int VPT, int C, int REG, bool R6>
+__device__ __forceinline__ void wire_fft_rest(float2* A, const FftPlan& plan, int tid, int T, const float2* tp,
+                                              bool inv) {
+    lds_barrier();
+    constexpr int p0 = (REG != 0 && (VPT == 2 || VPT == 4 || VPT == 8)) ? 1 : 0;
+    fft_lds_pm<VPT, C, 1, R6>(A, plan, tid, T, tp, inv, p0);
+}
+
+static bool plan_has6(const FftPlan& plan) {
+    for (int p = 0; p < plan.npass; ++p)
+        if (plan.radix[p] == 6) return true;
+    return false;
+}
+
 // One workgroup per tile of C consecutive time-frequency columns.
-template <int VPT, int C, int NT>
+template <int VPT, int C, int NT, int REG, bool R6>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_wire_fused(
     const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
@@ -382,10 +585,9 @@ void k_wire_fused(
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
-    float2* A = lds;               // [Wf][C]
-    float2* tw = lds + Wf * C;     // [Wf]
-    fill_full_table(tw, Wf, tid, T);
-    const TwFull twf{tw};
+    float2* A = lds;                                  // [Wf][C], padded
+    float2* tp = lds + lds_slots(Wf * C, 1);          // pass-major twiddles
+    build_pm_direct(tp, plan, tid, T);
     const int f0 = tile * C;
     const int nel = Wf * C;
     float2 acc[VPT];
@@ -406,7 +608,7 @@ void k_wire_fused(
     static_assert(NT % C == 0, "tile width must divide the thread count");
     const int c_own = tid % C, p_own = tid / C, f_own = min(f0 + c_own, F - 1);
     const bool f_ok = f0 + c_own < F;
-    // (the rows are loaded raw and masked only when stored to LDS: a select
+    // (the rows are loaded raw and masked only when they are used: a select
     // right after the loads would make the compiler wait for them before the
     // FFT they are meant to overlap)
     auto gather_s = [&](int k) {
@@ -432,18 +634,17 @@ void k_wire_fused(
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            int e = tid + i * T;
             const bool ok = f_ok && p_own + i * (NT / C) < n_wires;   // n_wires <= Wf
-            if (e < nel) A[e] = ok ? v[i] : make_float2(0.f, 0.f);
+            v[i] = ok ? v[i] : make_float2(0.f, 0.f);
         }
+        wire_fft_first<VPT, C, REG>(A, tid, T, v, nel, false);
         if (k + 1 < n_imp) gather_s(k + 1);
-        lds_barrier();
-        fft_lds<VPT, C>(A, plan, tid, T, twf, false);
+        wire_fft_rest<VPT, C, REG, R6>(A, plan, tid, T, tp, false);
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             int e = tid + i * T;
             if (e < nel) {
-                float2 a = A[e];
+                float2 a = A[lidx<1>(e)];
                 acc[i].x += a.x * r[i].x - a.y * r[i].y;
                 acc[i].y += a.x * r[i].y + a.y * r[i].x;
             }
@@ -451,19 +652,14 @@ void k_wire_fused(
         if (k + 1 < n_imp) gather_r(k + 1);
     }
     lds_barrier();
-#pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-        int e = tid + i * T;
-        if (e < nel) A[e] = acc[i];
-    }
-    lds_barrier();
-    fft_lds<VPT, C>(A, plan, tid, T, twf, true);
+    wire_fft_first<VPT, C, REG>(A, tid, T, acc, nel, true);
+    wire_fft_rest<VPT, C, REG, R6>(A, plan, tid, T, tp, true);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         int e = tid + i * T;
         if (e < nel) {
             int p = e / C, c = e % C, f = f0 + c;
-            if (p < n_wires && f < F) M[(int64_t)p * ldM + f] = A[e];
+            if (p < n_wires && f < F) M[(int64_t)p * ldM + f] = A[lidx<1>(e)];
         }
     }
 }
@@ -472,11 +668,20 @@ template <int VPT, int C, int NT>
 static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                               const FftPlan& plan, const float2* R, float2* M, int64_t ldM,
                               int batch, int64_t strideS, int64_t strideM, hipStream_t s) {
-    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
-    set_lds(k_wire_fused<VPT, C, NT>, lds);
+    const size_t lds = wire_lds_bytes(plan, C);
     dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(NT);
-    hipLaunchKernelGGL((k_wire_fused<VPT, C, NT>), grid, block, lds, s, S, ldS, n_wires, n_imp, F,
-                       plan, R, M, ldM, strideS, strideM, batch);
+    // the first pass in registers when each thread holds one butterfly's inputs
+    const bool reg = plan.radix[0] == VPT && NT * VPT == plan.n * C;
+#define LAR_WF(RG, S6)                                                                                  \
+    {                                                                                                   \
+        set_lds(k_wire_fused<VPT, C, NT, RG, S6>, lds);                                                 \
+        hipLaunchKernelGGL((k_wire_fused<VPT, C, NT, RG, S6>), grid, block, lds, s, S, ldS, n_wires, n_imp, \
+                           F, plan, R, M, ldM, strideS, strideM, batch);                                \
+    }
+    if (plan_has6(plan)) LAR_WF(0, true)
+    else if (reg) LAR_WF(1, false)
+    else LAR_WF(0, false)
+#undef LAR_WF
     return hipGetLastError();
 }
 
@@ -487,10 +692,9 @@ bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
     const bool shape = (cols == 4 && (threads == 256 || threads == 512)) ||
                        (cols == 8 && (threads == 256 || threads == 512 || threads == 1024)) ||
                        (cols == 16 && (threads == 512 || threads == 1024));
-    // the tile and its twiddle table must fit the 160 KB of LDS of a CU
-    const size_t lds = ((size_t)nw_fft * cols + nw_fft) * sizeof(float2);
-    return shape && vpt_for(nw_fft * cols, threads) && lds <= 160 * 1024 &&
-           make_plan(nw_fft, &plan, order);
+    // the tile and its twiddle tables must fit the 160 KB of LDS of a CU
+    if (!shape || !vpt_for(nw_fft * cols, threads) || !make_plan(nw_fft, &plan, order)) return false;
+    return wire_lds_bytes(plan, cols) <= kLdsBytes;
 }
 
 // Tiles of C time-frequency columns (8 by default: 64-byte row segments;

@@ -19,7 +19,8 @@ namespace lar {
 // Lengths are 2^a 3^b with passes of radix 8, 4, 3 and 2; the order of the
 // passes is a schedule choice (make_plan's `order`).
 constexpr int kMaxPasses = 16;
-constexpr int kPlanOrders = 4;
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
+constexpr int kPlanOrders = 5;
 
 struct FftPlan {
     int n;
@@ -30,7 +31,9 @@ struct FftPlan {
 // Host: build the plan for length n; false if n is not 2^a 3^b (n >= 1).
 // order 0: radix 8 passes first, then one 4 or 2, then the 3s; 1: radix 4
 // passes, then 3s, then one 2 (no radix 8); 2: 3s first, then 8s, then
-// 4/2; 3: the reverse of order 0.
+// 4/2; 3: the reverse of order 0; 4: radix 8 passes first, then each
+// remaining factor 2 paired with a 3 as a radix-6 pass, then what is left
+// (fewer passes when both 2 and 3 remain).
 bool make_plan(int n, FftPlan* plan, int order = 0);
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -110,6 +113,26 @@ __device__ __forceinline__ void dft_small<8>(float2* v, bool inv) {
     v[7] = csub(e[3], w3);
 }
 
+// 6-point DFT as 2 x 3: E = DFT3(x0, x2, x4), O = DFT3(x1, x3, x5), then
+// X[k] = E[k] + W6^k O[k] and X[k+3] = E[k] - W6^k O[k] (W6 = exp(-+2 pi i / 6)).
+template <>
+__device__ __forceinline__ void dft_small<6>(float2* v, bool inv) {
+    float2 e[3] = {v[0], v[2], v[4]};
+    float2 o[3] = {v[1], v[3], v[5]};
+    dft_small<3>(e, inv);
+    dft_small<3>(o, inv);
+    const float s3 = 0.86602540378443865f;
+    const float sg = inv ? 1.f : -1.f;
+    const float2 w1 = cmul(o[1], make_float2(0.5f, sg * s3));
+    const float2 w2 = cmul(o[2], make_float2(-0.5f, sg * s3));
+    v[0] = cadd(e[0], o[0]);
+    v[3] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], w1);
+    v[4] = csub(e[1], w1);
+    v[2] = cadd(e[2], w2);
+    v[5] = csub(e[2], w2);
+}
+
 // Twiddle accessors: tw(m) = exp(-2 pi i m / n) for 0 <= m < n.
 struct TwFull {           // table of n entries
     const float2* t;
@@ -171,8 +194,57 @@ __device__ __forceinline__ void stockham_pass(float2* A, int n, int Ns, int tid,
     lds_barrier();
 }
 
+// ---- transforms with pass-major twiddle tables and optional LDS padding
+//
+// LDS index with one float2 of padding after every 32 (PAD): the strided
+// writes of the first Stockham passes (stride R elements between lanes)
+// then spread over the LDS banks.
+template <int PAD>
+__device__ __forceinline__ int lidx(int i) { return PAD ? i + (i >> 5) : i; }
+// float2 slots of an n-element padded buffer
+__host__ __device__ inline int lds_slots(int n, int pad) { return pad ? n + (n >> 5) + 1 : n; }
+
+// stockham_pass of one sequence in a padded LDS buffer (lidx<1>).
+template <int R, int MAXB, class TW>
+__device__ __forceinline__ void stockham_pass_tw(float2* A, int n, int Ns, int tid, int T, const TW& tw, bool inv) {
+    const int nb = n / R;
+    const int stride = n / (Ns * R);
+    const bool ns_pow2 = (Ns & (Ns - 1)) == 0;
+    float2 v[MAXB][R];
+    int dst[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int j = tid + b * T;
+        dst[b] = -1;
+        if (j < nb) {
+            const int k = ns_pow2 ? (j & (Ns - 1)) : j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = A[lidx<1>(j + r * nb)];
+                if (r > 0) {
+                    const float2 t = tw(r * k * stride);
+                    x = inv ? cmulc(x, t) : cmul(x, t);
+                }
+                v[b][r] = x;
+            }
+            dst[b] = (j - k) * R + k;
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        if (dst[b] >= 0) {
+            dft_small<R>(v[b], inv);
+#pragma unroll
+            for (int r = 0; r < R; ++r) A[lidx<1>(dst[b] + r * Ns)] = v[b][r];
+        }
+    }
+    lds_barrier();
+}
+
 // Full transform of NS interleaved length-n sequences in LDS by T threads,
 // VPT >= n*NS/T values per thread.  Unnormalised; inv selects exp(+...).
+// Plans of radices 8, 4, 3 and 2 only (make_plan orders 0..3).
 template <int VPT, int NS, class TW>
 __device__ __forceinline__ void fft_lds(float2* A, const FftPlan& plan, int tid, int T,
                                         const TW& tw, bool inv) {
@@ -223,6 +295,101 @@ __device__ __forceinline__ double u52(uint32_t a, uint32_t b) {
     return (hi * 67108864.0 + lo + 0.5) * (1.0 / 4503599627370496.0);
 }
 
+
+// Pass-major twiddle tables: pass p (radix R, sub-transform size Ns) owns
+// Ns (R - 1) consecutive entries, entry k (R - 1) + r - 1 = exp(-2 pi i r k
+// stride / n) with stride = n / (Ns R), so a butterfly reads its R - 1
+// twiddles from consecutive slots with no index arithmetic.
+__host__ __device__ inline int pm_entries(const FftPlan& plan) {
+    int Ns = 1, e = 0;
+    for (int p = 0; p < plan.npass; ++p) {
+        e += Ns * (plan.radix[p] - 1);
+        Ns *= plan.radix[p];
+    }
+    return e;
+}
+
+template <class TW>
+__device__ __forceinline__ void build_pm(float2* tp, const FftPlan& plan, const TW& tw, int tid, int T) {
+    int Ns = 1, off = 0;
+    for (int p = 0; p < plan.npass; ++p) {
+        const int R = plan.radix[p], cnt = Ns * (R - 1), stride = plan.n / (Ns * R);
+        for (int e = tid; e < cnt; e += T) {
+            const int k = e / (R - 1), r = e - k * (R - 1) + 1;
+            tp[off + e] = tw(r * k * stride);
+        }
+        off += cnt;
+        Ns *= R;
+    }
+}
+
+// One Stockham pass as stockham_pass, twiddles from the pass's table tp.
+template <int R, int MAXB, int NS, int PAD>
+__device__ __forceinline__ void stockham_pass_pm(float2* A, int n, int Ns, int tid, int T, const float2* tp,
+                                                 bool inv) {
+    const int nb = n / R;
+    const int total = nb * NS;
+    const bool ns_pow2 = (Ns & (Ns - 1)) == 0;
+    float2 v[MAXB][R];
+    int dst[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int w = tid + b * T;
+        dst[b] = -1;
+        if (w < total) {
+            const int s = w % NS, j = w / NS;
+            const int k = ns_pow2 ? (j & (Ns - 1)) : j % Ns;
+            const float2* t = tp + k * (R - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float2 x = A[lidx<PAD>((j + r * nb) * NS + s)];
+                if (r > 0) x = inv ? cmulc(x, t[r - 1]) : cmul(x, t[r - 1]);
+                v[b][r] = x;
+            }
+            dst[b] = ((j - k) * R + k) * NS + s;
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        if (dst[b] >= 0) {
+            dft_small<R>(v[b], inv);
+#pragma unroll
+            for (int r = 0; r < R; ++r) A[lidx<PAD>(dst[b] + r * Ns * NS)] = v[b][r];
+        }
+    }
+    lds_barrier();
+}
+
+// Passes p0.. of a transform of NS interleaved sequences (as fft_lds),
+// with the pass-major tables tp of build_pm (passes before p0 were done
+// elsewhere, e.g. in registers).  R6: the plan may hold radix-6 passes
+// (without it the radix-6 case is not compiled in, which keeps the
+// registers of the other passes' kernels down).
+template <int VPT, int NS, int PAD, bool R6 = true>
+__device__ __forceinline__ void fft_lds_pm(float2* A, const FftPlan& plan, int tid, int T, const float2* tp,
+                                           bool inv, int p0 = 0) {
+    int Ns = 1;
+    for (int p = 0; p < p0; ++p) {
+        tp += Ns * (plan.radix[p] - 1);
+        Ns *= plan.radix[p];
+    }
+    for (int p = p0; p < plan.npass; ++p) {
+        const int R = plan.radix[p];
+        if (R == 8)
+            stockham_pass_pm<8, (VPT + 7) / 8, NS, PAD>(A, plan.n, Ns, tid, T, tp, inv);
+        else if (R6 && R == 6)
+            stockham_pass_pm<6, (VPT + 5) / 6, NS, PAD>(A, plan.n, Ns, tid, T, tp, inv);
+        else if (R == 4)
+            stockham_pass_pm<4, (VPT + 3) / 4, NS, PAD>(A, plan.n, Ns, tid, T, tp, inv);
+        else if (R == 3)
+            stockham_pass_pm<3, (VPT + 2) / 3, NS, PAD>(A, plan.n, Ns, tid, T, tp, inv);
+        else
+            stockham_pass_pm<2, (VPT + 1) / 2, NS, PAD>(A, plan.n, Ns, tid, T, tp, inv);
+        tp += Ns * (R - 1);
+        Ns *= R;
+    }
+}
 
 // blockIdx -> tile with consecutive tiles on one XCD (workgroups are dealt
 // round-robin over the 8 XCDs, each with its own L2).

@@ -175,8 +175,8 @@ def test_schedule_registry_host_side(lar):
         lar.schedule_set(P, None)
     assert lar.schedule_get(P) == d
     # Tf/2 = 3072 over 256 threads is 12 values per thread; 4 x 1024 is not a
-    # wire shape; radix order 4 does not exist; 16 x 512 is 16 values of Wf 512
-    for bad in (dict(row_threads=256), dict(wire_cols=4, wire_threads=1024), dict(row_order=4),
+    # wire shape; radix order 5 does not exist; 16 x 512 is 16 values of Wf 512
+    for bad in (dict(row_threads=256), dict(wire_cols=4, wire_threads=1024), dict(row_order=5),
                 dict(wire_order=-1), dict(wire_cols=16, wire_threads=512), dict(row_threads=300)):
         with pytest.raises(lar.LarError) as e:
             lar.schedule_set(P, dict(d, **bad))
@@ -204,4 +204,6 @@ def test_schedule_candidates_every_shape_valid(lar):
         finally:
             lar.schedule_set(P, None)
     wire_orders = {c["wire_order"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
-    assert wire_orders == {0, 1}            # 512 = 8^3: orders 2 and 3 repeat order 0
+    assert wire_orders == {0, 1}            # 512 = 8^3: orders 2, 3 and 4 repeat order 0
+    row_orders = {c["row_order"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
+    assert 4 in row_orders                  # 3072 = 8 8 8 6 with a radix-6 pass
