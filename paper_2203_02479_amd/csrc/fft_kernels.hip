@@ -392,8 +392,15 @@ static int vpt_for(int n, int T) {
     return 0;
 }
 
+// Rows: Nh/8 threads when that is a listed size (each thread then holds the
+// 8 inputs of one first-pass butterfly and that pass runs in registers;
+// measured fastest at Tf = 6144), else 256 / 512 / 1024 by length.
 int default_row_threads(int nt_fft) {
     const int Nh = nt_fft / 2;
+    if (Nh % 8 == 0) {
+        const int t = Nh / 8;
+        if (t == 256 || t == 384 || t == 512 || t == 768 || t == 1024) return t;
+    }
     return Nh <= 1024 ? 256 : Nh <= 4096 ? 512 : 1024;
 }
 

@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for the kernels of this package.
 
     python -m paper_2203_02479_amd.profsum stats DIR
-        per-kernel calls / average / total time from a --kernel-trace --stats run
+        per-kernel calls / average / total time from a --kernel-trace --stats run,
+        then per (kernel, grid size) the launch count and median duration
     python -m paper_2203_02479_amd.profsum pmc DIR COUNTER [--last N]
         per-kernel mean of COUNTER over the last N dispatches of each kernel
         (a --pmc run; FETCH_SIZE / WRITE_SIZE are KiB per dispatch)
@@ -74,6 +75,23 @@ def stats(d):
     return out
 
 
+def launch_medians(d):
+    """{(kernel, grid size): (launches, median us)} from the kernel trace:
+    launches of one kernel with different grids (different row counts,
+    batch sizes) are kept apart, and the median is not moved by the first,
+    cold launch the way the average is."""
+    try:
+        path = _find(d, "kernel_trace.csv")
+    except FileNotFoundError:
+        return {}
+    per = {}
+    for r in csv.DictReader(open(path)):
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        key = (_short(r["Kernel_Name"]), int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0))
+        per.setdefault(key, []).append(us)
+    return {k: (len(v), statistics.median(v)) for k, v in per.items()}
+
+
 def _pmc_rows(d, counter):
     rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
     per = {}
@@ -138,6 +156,11 @@ def main(argv):
         print(f"{'calls':>6} {'avg_us':>10} {'total_ms':>10}  kernel")
         for name, calls, avg, tot in sorted(stats(argv[1]), key=lambda r: -r[3]):
             print(f"{calls:6d} {avg:10.2f} {tot:10.3f}  {name}")
+        med = launch_medians(argv[1])
+        if med:
+            print(f"\nper launch shape (grid threads): launches, median us")
+            for (name, grid), (n, m) in sorted(med.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+                print(f"{n:6d} {m:10.2f} {grid:10d}  {name}")
     elif cmd == "pmc":
         last = 2
         if "--last" in argv:
