@@ -8,6 +8,9 @@
 //               the response spectrum of offset k and accumulate; then one
 //               inverse FFT over wires.  The impact-offset reduction never
 //               leaves the chip.
+//  k_wire_888   the same for Wf = 512 with the 8 8 8 plan fixed at compile
+//               time (first and last pass in registers, two barriers per
+//               offset).
 //  k_c2r_rows   inverse real FFT along ticks, scaled by 1/(Wf Tf), cropped.
 //
 // All three are bound by HBM traffic: every transform lives in LDS and each
@@ -671,6 +674,135 @@ void k_wire_fused(
     }
 }
 
+// The wire pass for Wf = 512 with the radix-8 plan (8 8 8) fixed at compile
+// time, one butterfly per thread and pass (T = 64 C).  Thread (j, s) =
+// (tid / C, tid % C) holds wires j + 64 r, r = 0..7, of column s: exactly
+// the inputs of its first-pass butterfly and the outputs of its last-pass
+// butterfly.  So per impact offset the gathered rows go through the first
+// pass in registers, one LDS exchange into the second pass, a second
+// exchange (into a second buffer, which spares the barrier that an in-place
+// pass needs between its reads and writes) into the third, and the third
+// pass's outputs meet the response slab in registers: two barriers per
+// offset, and every LDS index is a thread constant plus a compile-time
+// offset.  The sum over offsets goes through the same three passes inverted.
+template <int C, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_wire_888(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
+                const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
+                int64_t strideM, int batch) {
+    constexpr int N = 512, SL = N * C + N * C / 32;   // padded slots of one [Wf][C] buffer
+    static_assert(NT == 64 * C, "one butterfly per thread and pass");
+    extern __shared__ float2 lds[];
+    float2* A = lds;
+    float2* B = lds + SL;
+    float2* tp = B + SL;   // pass-major twiddles: pass 1 from entry 7, pass 2 from entry 63
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = lin / batch, item = lin - tile * batch;
+    S += (int64_t)item * strideS;
+    M += (int64_t)item * strideM;
+    const int tid = threadIdx.x;
+    build_pm_direct(tp, plan, tid, NT);
+    const float2* tp1 = tp + 7;
+    const float2* tp2 = tp + 63;
+    const int f0 = tile * C, s = tid % C, j = tid / C, k1 = j & 7;
+    const int f = min(f0 + s, F - 1);
+    const bool f_ok = f0 + s < F;
+    // padded LDS slots: first-pass outputs j 8 + r, second-pass inputs (and
+    // third-pass inputs) j + 64 r, second-pass outputs (j - k1) 8 + k1 + 8 r;
+    // 64 C slots hold 2 C pad slots, so r 64 C advances a padded index by r (64 C + 2 C)
+    const int e0 = j * 8 * C + s;
+    const int li1 = lidx<1>(j * C + s);
+    const int d1 = ((j - k1) * 8 + k1) * C + s;
+    float2 v[8], rr[8], acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = make_float2(0.f, 0.f);
+    // the gathers are unconditional (clamped rows, values masked at use) so
+    // that a thread's loads are in flight together; the row index passes
+    // through an empty asm so that the addresses are rebuilt per gather
+    // rather than held in registers across the offset loop
+    auto gather_s = [&](int k) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int p = j + 64 * r;
+            asm volatile("" : "+v"(p));
+            v[r] = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + f];
+        }
+    };
+    auto gather_r = [&](int k) {
+        const float2* Rk = R + (int64_t)k * N * F;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            int p = j + 64 * r;
+            asm volatile("" : "+v"(p));
+            rr[r] = Rk[(int64_t)p * F + f];
+        }
+    };
+    auto fft = [&](float2 (&x)[8], bool inv) {
+        dft_small<8>(x, inv);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) A[lidx<1>(e0 + r * C)] = x[r];
+        lds_barrier();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            float2 y = A[li1 + r * 66 * C];
+            if (r > 0) y = inv ? cmulc(y, tp1[k1 * 7 + r - 1]) : cmul(y, tp1[k1 * 7 + r - 1]);
+            x[r] = y;
+        }
+        dft_small<8>(x, inv);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) B[lidx<1>(d1 + r * 8 * C)] = x[r];
+        lds_barrier();
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            float2 y = B[li1 + r * 66 * C];
+            if (r > 0) y = inv ? cmulc(y, tp2[j * 7 + r - 1]) : cmul(y, tp2[j * 7 + r - 1]);
+            x[r] = y;
+        }
+        dft_small<8>(x, inv);
+    };
+    gather_s(0);
+    gather_r(0);
+    for (int k = 0; k < n_imp; ++k) {
+        float2 x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const bool ok = f_ok && j + 64 * r < n_wires;
+            x[r] = ok ? v[r] : make_float2(0.f, 0.f);
+        }
+        if (k + 1 < n_imp) gather_s(k + 1);
+        fft(x, false);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            acc[r].x += x[r].x * rr[r].x - x[r].y * rr[r].y;
+            acc[r].y += x[r].x * rr[r].y + x[r].y * rr[r].x;
+        }
+        if (k + 1 < n_imp) gather_r(k + 1);
+    }
+    fft(acc, true);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int p = j + 64 * r;
+        if (p < n_wires && f_ok) M[(int64_t)p * ldM + f0 + s] = acc[r];
+    }
+}
+
+static bool plan_is_888(const FftPlan& plan) {
+    return plan.n == 512 && plan.npass == 3 && plan.radix[0] == 8 && plan.radix[1] == 8 && plan.radix[2] == 8;
+}
+
+template <int C>
+static hipError_t wire_launch_888(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
+                                  const FftPlan& plan, const float2* R, float2* M, int64_t ldM, int batch,
+                                  int64_t strideS, int64_t strideM, hipStream_t s) {
+    constexpr int SL = 512 * C + 512 * C / 32;
+    const size_t lds = (size_t)(2 * SL + pm_entries(plan)) * sizeof(float2);
+    dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(64 * C);
+    set_lds(k_wire_888<C, 64 * C>, lds);
+    hipLaunchKernelGGL((k_wire_888<C, 64 * C>), grid, block, lds, s, S, ldS, n_wires, n_imp, F, plan, R, M, ldM,
+                       strideS, strideM, batch);
+    return hipGetLastError();
+}
+
 template <int VPT, int C, int NT>
 static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                               const FftPlan& plan, const float2* R, float2* M, int64_t ldM,
@@ -701,6 +833,8 @@ bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
                        (cols == 16 && (threads == 512 || threads == 1024));
     // the tile and its twiddle tables must fit the 160 KB of LDS of a CU
     if (!shape || !vpt_for(nw_fft * cols, threads) || !make_plan(nw_fft, &plan, order)) return false;
+    if (plan_is_888(plan) && threads == 64 * cols)   // k_wire_888: two [Wf][C] buffers
+        return (size_t)(2 * (512 * cols + 16 * cols) + pm_entries(plan)) * sizeof(float2) <= kLdsBytes;
     return wire_lds_bytes(plan, cols) <= kLdsBytes;
 }
 
@@ -718,6 +852,11 @@ hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_im
     if (!wire_sched_ok(nw_fft, cols, threads, order) || !make_plan(nw_fft, &plan, order))
         return hipErrorInvalidValue;
     if (F <= 0 || batch <= 0) return hipSuccess;
+    if (plan_is_888(plan) && threads == 64 * cols) {
+        if (cols == 4) return wire_launch_888<4>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
+        if (cols == 8) return wire_launch_888<8>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
+        if (cols == 16) return wire_launch_888<16>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
+    }
     const int vpt = vpt_for(nw_fft * cols, threads);
 #define LAR_W(V, C, T)                                                                          \
     case (C) * 100000 + (T) * 16 + (V):                                                         \
