@@ -8,9 +8,9 @@
 //               the response spectrum of offset k and accumulate; then one
 //               inverse FFT over wires.  The impact-offset reduction never
 //               leaves the chip.
-//  k_wire_888   the same for Wf = 512 with the 8 8 8 plan fixed at compile
-//               time (first and last pass in registers, two barriers per
-//               offset).
+//  k_wire_static the same with the plan fixed at compile time (Wf = 512,
+//               8 8 8): first and last pass in registers, two barriers per
+//               offset.
 //  k_c2r_rows   inverse real FFT along ticks, scaled by 1/(Wf Tf), cropped.
 //
 // All three are bound by HBM traffic: every transform lives in LDS and each
@@ -674,56 +674,117 @@ void k_wire_fused(
     }
 }
 
-// The wire pass for Wf = 512 with the radix-8 plan (8 8 8) fixed at compile
-// time, one butterfly per thread and pass (T = 64 C).  Thread (j, s) =
-// (tid / C, tid % C) holds wires j + 64 r, r = 0..7, of column s: exactly
-// the inputs of its first-pass butterfly and the outputs of its last-pass
-// butterfly.  So per impact offset the gathered rows go through the first
-// pass in registers, one LDS exchange into the second pass, a second
-// exchange (into a second buffer, which spares the barrier that an in-place
-// pass needs between its reads and writes) into the third, and the third
-// pass's outputs meet the response slab in registers: two barriers per
-// offset, and every LDS index is a thread constant plus a compile-time
-// offset.  The sum over offsets goes through the same three passes inverted.
-template <int C, int NT>
+// The wire pass with its plan fixed at compile time: radices R0, Rm..., R0
+// (first and last radix equal) over N wires, one first- and last-pass
+// butterfly per thread (T = C N / R0).  Thread (j, s) = (tid / C, tid % C)
+// holds wires j + (N / R0) r, r < R0, of column s: exactly the inputs of its
+// first-pass butterfly and the outputs of its last-pass one (a Stockham last
+// pass writes butterfly j's outputs to j + r N / R0).  So per impact offset
+// the gathered rows go through the first pass in registers, the middle
+// passes between two LDS buffers (no barrier between a pass's reads and its
+// writes), the last pass back into registers, where its outputs meet the
+// response slab: one barrier per pass but the last, and every LDS index is
+// a thread constant plus a compile-time offset.  The sum over offsets goes
+// through the same passes inverted.
+template <int... Rs>
+struct RadixList {};
+template <int... Rs>
+struct RadixProd {
+    static constexpr int v = 1;
+};
+template <int R, int... Rs>
+struct RadixProd<R, Rs...> {
+    static constexpr int v = R * RadixProd<Rs...>::v;
+};
+// entries of the pass-major table taken by passes of radices Rs from Ns = NS on
+template <int NS, int... Rs>
+struct TableSpan {
+    static constexpr int v = 0;
+};
+template <int NS, int R, int... Rs>
+struct TableSpan<NS, R, Rs...> {
+    static constexpr int v = NS * (R - 1) + TableSpan<NS * R, Rs...>::v;
+};
+
+// One middle Stockham pass (radix R, sub-transform size NS) of C interleaved
+// N-point transforms from src to dst (both padded).
+template <int N, int C, int NT, int NS, int R>
+__device__ __forceinline__ void static_pass(const float2* __restrict__ src, float2* __restrict__ dst,
+                                            const float2* __restrict__ tw, int tid, bool inv) {
+    constexpr int NB = N / R, TOT = NB * C, MAXB = (TOT + NT - 1) / NT;
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int w = tid + m * NT;
+        if (TOT % NT == 0 || w < TOT) {
+            const int s = w % C, b = w / C, k = b % NS;
+            const int ib = b * C + s, li = lidx<1>(ib);
+            float2 x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                // (when NB C is a multiple of 32 the pad advances by exactly NB C / 32)
+                float2 y = src[(NB * C) % 32 == 0 ? li + r * (NB * C + NB * C / 32) : lidx<1>(ib + r * NB * C)];
+                if (r > 0) y = inv ? cmulc(y, tw[k * (R - 1) + r - 1]) : cmul(y, tw[k * (R - 1) + r - 1]);
+                x[r] = y;
+            }
+            dft_small<R>(x, inv);
+            const int ob = ((b - k) * R + k) * C + s, lo = lidx<1>(ob);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                dst[(NS * C) % 32 == 0 ? lo + r * (NS * C + NS * C / 32) : lidx<1>(ob + r * NS * C)] = x[r];
+        }
+    }
+}
+
+template <int N, int C, int NT, int NS, int TOFF>
+__device__ __forceinline__ void static_mid(RadixList<>, float2*&, float2*&, const float2*, int, bool) {}
+template <int N, int C, int NT, int NS, int TOFF, int R, int... Rest>
+__device__ __forceinline__ void static_mid(RadixList<R, Rest...>, float2*& src, float2*& dst, const float2* tp,
+                                           int tid, bool inv) {
+    static_pass<N, C, NT, NS, R>(src, dst, tp + TOFF, tid, inv);
+    lds_barrier();
+    float2* t = src;
+    src = dst;
+    dst = t;
+    static_mid<N, C, NT, NS * R, TOFF + NS * (R - 1)>(RadixList<Rest...>{}, src, dst, tp, tid, inv);
+}
+
+template <int N, int C, int NT, int R0, int... Rm>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_wire_888(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
-                const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
-                int64_t strideM, int batch) {
-    constexpr int N = 512, SL = N * C + N * C / 32;   // padded slots of one [Wf][C] buffer
-    static_assert(NT == 64 * C, "one butterfly per thread and pass");
+void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
+                   const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
+                   int64_t strideM, int batch) {
+    constexpr int NB = N / R0, SL = N * C + N * C / 32;   // padded slots of one [Wf][C] buffer
+    constexpr int P = 2 + sizeof...(Rm);                 // passes
+    constexpr int TL = R0 - 1 + TableSpan<R0, Rm...>::v; // table entry of the last pass
+    static_assert(NB * C == NT, "one first- and last-pass butterfly per thread");
+    static_assert(R0 * RadixProd<Rm...>::v * R0 == N, "plan length");
     extern __shared__ float2 lds[];
-    float2* A = lds;
-    float2* B = lds + SL;
-    float2* tp = B + SL;   // pass-major twiddles: pass 1 from entry 7, pass 2 from entry 63
+    float2* buf0 = lds;
+    float2* buf1 = lds + SL;
+    float2* tp = buf1 + SL;   // pass-major twiddles
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tile = lin / batch, item = lin - tile * batch;
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
     const int tid = threadIdx.x;
     build_pm_direct(tp, plan, tid, NT);
-    const float2* tp1 = tp + 7;
-    const float2* tp2 = tp + 63;
-    const int f0 = tile * C, s = tid % C, j = tid / C, k1 = j & 7;
+    const int f0 = tile * C, s = tid % C, j = tid / C;
     const int f = min(f0 + s, F - 1);
     const bool f_ok = f0 + s < F;
-    // padded LDS slots: first-pass outputs j 8 + r, second-pass inputs (and
-    // third-pass inputs) j + 64 r, second-pass outputs (j - k1) 8 + k1 + 8 r;
-    // 64 C slots hold 2 C pad slots, so r 64 C advances a padded index by r (64 C + 2 C)
-    const int e0 = j * 8 * C + s;
-    const int li1 = lidx<1>(j * C + s);
-    const int d1 = ((j - k1) * 8 + k1) * C + s;
-    float2 v[8], rr[8], acc[8];
+    const int e0 = j * R0 * C + s;        // first-pass outputs j R0 + r
+    const int i1 = j * C + s;             // last-pass inputs j + NB r
+    const int li1 = lidx<1>(i1);
+    float2 v[R0], rr[R0], acc[R0];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = make_float2(0.f, 0.f);
+    for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
     // the gathers are unconditional (clamped rows, values masked at use) so
     // that a thread's loads are in flight together; the row index passes
     // through an empty asm so that the addresses are rebuilt per gather
     // rather than held in registers across the offset loop
     auto gather_s = [&](int k) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            int p = j + 64 * r;
+        for (int r = 0; r < R0; ++r) {
+            int p = j + NB * r;
             asm volatile("" : "+v"(p));
             v[r] = S[(int64_t)(min(p, n_wires - 1) * n_imp + k) * ldS + f];
         }
@@ -731,48 +792,48 @@ void k_wire_888(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_im
     auto gather_r = [&](int k) {
         const float2* Rk = R + (int64_t)k * N * F;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            int p = j + 64 * r;
+        for (int r = 0; r < R0; ++r) {
+            int p = j + NB * r;
             asm volatile("" : "+v"(p));
             rr[r] = Rk[(int64_t)p * F + f];
         }
     };
-    auto fft = [&](float2 (&x)[8], bool inv) {
-        dft_small<8>(x, inv);
+    // With an even number of passes the last pass reads the buffer the
+    // first pass writes, so successive transforms start on alternate buffers
+    // (the first pass of one then never overwrites what the last pass of the
+    // previous one may still be reading).
+    int par = 0;
+    auto fft = [&](float2 (&x)[R0], bool inv) {
+        float2* a = (P % 2 == 0 && par) ? buf1 : buf0;
+        float2* b = (P % 2 == 0 && par) ? buf0 : buf1;
+        par ^= 1;
+        dft_small<R0>(x, inv);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) A[lidx<1>(e0 + r * C)] = x[r];
+        for (int r = 0; r < R0; ++r) a[lidx<1>(e0 + r * C)] = x[r];
         lds_barrier();
+        static_mid<N, C, NT, R0, R0 - 1>(RadixList<Rm...>{}, a, b, tp, tid, inv);
+        const float2* tl = tp + TL;   // a holds the last pass's inputs
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            float2 y = A[li1 + r * 66 * C];
-            if (r > 0) y = inv ? cmulc(y, tp1[k1 * 7 + r - 1]) : cmul(y, tp1[k1 * 7 + r - 1]);
+        for (int r = 0; r < R0; ++r) {
+            float2 y = a[(NB * C) % 32 == 0 ? li1 + r * (NB * C + NB * C / 32) : lidx<1>(i1 + r * NB * C)];
+            if (r > 0) y = inv ? cmulc(y, tl[j * (R0 - 1) + r - 1]) : cmul(y, tl[j * (R0 - 1) + r - 1]);
             x[r] = y;
         }
-        dft_small<8>(x, inv);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) B[lidx<1>(d1 + r * 8 * C)] = x[r];
-        lds_barrier();
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            float2 y = B[li1 + r * 66 * C];
-            if (r > 0) y = inv ? cmulc(y, tp2[j * 7 + r - 1]) : cmul(y, tp2[j * 7 + r - 1]);
-            x[r] = y;
-        }
-        dft_small<8>(x, inv);
+        dft_small<R0>(x, inv);
     };
     gather_s(0);
     gather_r(0);
     for (int k = 0; k < n_imp; ++k) {
-        float2 x[8];
+        float2 x[R0];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const bool ok = f_ok && j + 64 * r < n_wires;
+        for (int r = 0; r < R0; ++r) {
+            const bool ok = f_ok && j + NB * r < n_wires;
             x[r] = ok ? v[r] : make_float2(0.f, 0.f);
         }
         if (k + 1 < n_imp) gather_s(k + 1);
         fft(x, false);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
+        for (int r = 0; r < R0; ++r) {
             acc[r].x += x[r].x * rr[r].x - x[r].y * rr[r].y;
             acc[r].y += x[r].x * rr[r].y + x[r].y * rr[r].x;
         }
@@ -780,26 +841,30 @@ void k_wire_888(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_im
     }
     fft(acc, true);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int p = j + 64 * r;
+    for (int r = 0; r < R0; ++r) {
+        const int p = j + NB * r;
         if (p < n_wires && f_ok) M[(int64_t)p * ldM + f0 + s] = acc[r];
     }
 }
 
+// Wf = 512 with the plan 8 8 8 and T = 64 C takes k_wire_static.
 static bool plan_is_888(const FftPlan& plan) {
     return plan.n == 512 && plan.npass == 3 && plan.radix[0] == 8 && plan.radix[1] == 8 && plan.radix[2] == 8;
+}
+static size_t static_lds_bytes(const FftPlan& plan, int C) {
+    return (size_t)(2 * (plan.n * C + plan.n * C / 32) + pm_entries(plan)) * sizeof(float2);
 }
 
 template <int C>
 static hipError_t wire_launch_888(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
                                   const FftPlan& plan, const float2* R, float2* M, int64_t ldM, int batch,
                                   int64_t strideS, int64_t strideM, hipStream_t s) {
-    constexpr int SL = 512 * C + 512 * C / 32;
-    const size_t lds = (size_t)(2 * SL + pm_entries(plan)) * sizeof(float2);
+    const size_t lds = static_lds_bytes(plan, C);
     dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(64 * C);
-    set_lds(k_wire_888<C, 64 * C>, lds);
-    hipLaunchKernelGGL((k_wire_888<C, 64 * C>), grid, block, lds, s, S, ldS, n_wires, n_imp, F, plan, R, M, ldM,
-                       strideS, strideM, batch);
+    auto kern = k_wire_static<512, C, 64 * C, 8, 8>;
+    set_lds(kern, lds);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, S, ldS, n_wires, n_imp, F, plan, R, M, ldM, strideS, strideM,
+                       batch);
     return hipGetLastError();
 }
 
@@ -824,7 +889,11 @@ static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_i
     return hipGetLastError();
 }
 
-int default_wire_threads(int nw_fft) { return nw_fft <= 512 ? 512 : 1024; }
+// Default wire tiles: 16 columns x 1024 threads for Wf = 512 (k_wire_static,
+// whole 128-byte row segments), 8 x 512 below, 4 x 512 above (more resident
+// workgroups per CU).
+int default_wire_cols(int nw_fft) { return nw_fft == 512 ? 16 : (nw_fft < 512 ? 8 : 4); }
+int default_wire_threads(int nw_fft) { return nw_fft == 512 ? 1024 : 512; }
 
 bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
     FftPlan plan;
@@ -833,20 +902,19 @@ bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
                        (cols == 16 && (threads == 512 || threads == 1024));
     // the tile and its twiddle tables must fit the 160 KB of LDS of a CU
     if (!shape || !vpt_for(nw_fft * cols, threads) || !make_plan(nw_fft, &plan, order)) return false;
-    if (plan_is_888(plan) && threads == 64 * cols)   // k_wire_888: two [Wf][C] buffers
-        return (size_t)(2 * (512 * cols + 16 * cols) + pm_entries(plan)) * sizeof(float2) <= kLdsBytes;
+    if (plan_is_888(plan) && threads == 64 * cols)   // k_wire_static: two [Wf][C] buffers
+        return static_lds_bytes(plan, cols) <= kLdsBytes;
     return wire_lds_bytes(plan, cols) <= kLdsBytes;
 }
 
-// Tiles of C time-frequency columns (8 by default: 64-byte row segments;
-// neighbouring tiles run on one XCD and share its L2 lines) by T threads
-// (512 by default, 1024 for Wf > 512), so that a thread holds at most 8
-// values per tile array.
+// Tiles of C time-frequency columns (neighbouring tiles run on one XCD and
+// share its L2 lines) by T threads, so that a thread holds at most 8 values
+// per tile array; defaults as default_wire_cols / default_wire_threads.
 hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_imp, int nw_fft,
                              int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
                              int batch, int64_t strideS, int64_t strideM, int cols, int threads,
                              int order) {
-    if (!cols) cols = 8;
+    if (!cols) cols = default_wire_cols(nw_fft);
     if (!threads) threads = default_wire_threads(nw_fft);
     FftPlan plan;
     if (!wire_sched_ok(nw_fft, cols, threads, order) || !make_plan(nw_fft, &plan, order))

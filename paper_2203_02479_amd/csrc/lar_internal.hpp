@@ -410,6 +410,7 @@ struct Sched {
     int wire_cols, wire_threads, wire_order;
 };
 int default_row_threads(int nt_fft);
+int default_wire_cols(int nw_fft);
 int default_wire_threads(int nw_fft);
 bool row_sched_ok(int nt_fft, int threads, int order);
 bool wire_sched_ok(int nw_fft, int cols, int threads, int order);

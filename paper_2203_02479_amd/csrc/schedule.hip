@@ -28,7 +28,7 @@ Sched sched_default(int nt_fft, int nw_fft) {
     Sched s;
     s.row_threads = default_row_threads(nt_fft);
     s.row_order = 4;   // radix 8 first, 2 x 3 merged into radix 6
-    s.wire_cols = 8;
+    s.wire_cols = default_wire_cols(nw_fft);
     s.wire_threads = default_wire_threads(nw_fft);
     s.wire_order = 0;
     return s;

@@ -160,7 +160,7 @@ def test_stage_calls_host_side_errors(lar):
 def test_schedule_registry_host_side(lar):
     P = inputs.cfg1_plane()
     d = lar.schedule_default(P)
-    assert d == dict(row_threads=384, row_order=4, wire_cols=8, wire_threads=512, wire_order=0)
+    assert d == dict(row_threads=384, row_order=4, wire_cols=16, wire_threads=1024, wire_order=0)
     assert lar.schedule_get(P) == d
     cands = lar.schedule_candidates(P)
     assert cands[0] == d and len(cands) == len({tuple(c.values()) for c in cands})
