@@ -10,7 +10,8 @@
 //               leaves the chip.
 //  k_wire_static the same with the plan fixed at compile time (Wf = 512,
 //               8 8 8): first and last pass in registers, two barriers per
-//               offset.
+//               offset; k_wire_adjoint_static and k_wire_adjoint_items_static
+//               likewise for the adjoint.
 //  k_c2r_rows   inverse real FFT along ticks, scaled by 1/(Wf Tf), cropped.
 //
 // All three are bound by HBM traffic: every transform lives in LDS and each
@@ -748,32 +749,82 @@ __device__ __forceinline__ void static_mid(RadixList<R, Rest...>, float2*& src, 
     static_mid<N, C, NT, NS * R, TOFF + NS * (R - 1)>(RadixList<Rest...>{}, src, dst, tp, tid, inv);
 }
 
+// C interleaved N-point transforms over wires with the plan fixed at compile
+// time, for a workgroup of NT = C N / R0 threads: thread (j, s) holds the
+// values at j + (N / R0) r, r < R0, of column s on entry and on exit (the
+// inputs of its first-pass butterfly, the outputs of its last-pass one).
+// The LDS holds two padded [N][C] buffers and the pass-major twiddles.
+template <int N, int C, int NT, int R0, int... Rm>
+struct StaticFft {
+    static constexpr int NB = N / R0;                      // wire stride of a thread's values
+    static constexpr int SL = N * C + N * C / 32;          // padded slots of one buffer
+    static constexpr int P = 2 + sizeof...(Rm);            // passes
+    static constexpr int TL = R0 - 1 + TableSpan<R0, Rm...>::v;   // table entry of the last pass
+    static_assert(NB * C == NT, "one first- and last-pass butterfly per thread");
+    static_assert(R0 * RadixProd<Rm...>::v * R0 == N, "plan length");
+    float2* buf0;
+    float2* buf1;
+    float2* tp;
+    int tid, j, s, e0, i1, li1, par;
+    // builds the twiddle table (callers synchronise before the first run)
+    __device__ StaticFft(float2* lds, const FftPlan& plan, int tid_)
+        : buf0(lds), buf1(lds + SL), tp(lds + 2 * SL), tid(tid_), j(tid_ / C), s(tid_ % C), par(0) {
+        e0 = j * R0 * C + s;
+        i1 = j * C + s;
+        li1 = lidx<1>(i1);
+        build_pm_direct(tp, plan, tid, NT);
+    }
+    static size_t lds_bytes(const FftPlan& plan) {
+        return (size_t)(2 * SL + pm_entries(plan)) * sizeof(float2);
+    }
+    // x <- the (inverse with inv) transform of x.  With an even number of
+    // passes the last pass reads the buffer the first pass writes, so
+    // successive transforms start on alternate buffers: the first pass of
+    // one then never overwrites what the last pass of the previous one may
+    // still be reading.
+    __device__ __forceinline__ void run(float2 (&x)[R0], bool inv) {
+        float2* a = (P % 2 == 0 && par) ? buf1 : buf0;
+        float2* b = (P % 2 == 0 && par) ? buf0 : buf1;
+        par ^= 1;
+        dft_small<R0>(x, inv);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) a[lidx<1>(e0 + r * C)] = x[r];
+        lds_barrier();
+        static_mid<N, C, NT, R0, R0 - 1>(RadixList<Rm...>{}, a, b, tp, tid, inv);
+        const float2* tl = tp + TL;   // a holds the last pass's inputs
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            float2 y = a[(NB * C) % 32 == 0 ? li1 + r * (NB * C + NB * C / 32) : lidx<1>(i1 + r * NB * C)];
+            if (r > 0) y = inv ? cmulc(y, tl[j * (R0 - 1) + r - 1]) : cmul(y, tl[j * (R0 - 1) + r - 1]);
+            x[r] = y;
+        }
+        dft_small<R0>(x, inv);
+    }
+};
+
+// The wire pass with a compile-time plan: per impact offset the gathered
+// rows go through the first pass in registers, the middle passes between
+// two LDS buffers (no barrier between a pass's reads and its writes), and
+// the last pass back into registers, where its outputs meet the response
+// slab: one barrier per pass but the last, and every LDS index is a thread
+// constant plus a compile-time offset.  The sum over offsets goes through
+// the same passes inverted.
 template <int N, int C, int NT, int R0, int... Rm>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
                    const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
                    int64_t strideM, int batch) {
-    constexpr int NB = N / R0, SL = N * C + N * C / 32;   // padded slots of one [Wf][C] buffer
-    constexpr int P = 2 + sizeof...(Rm);                 // passes
-    constexpr int TL = R0 - 1 + TableSpan<R0, Rm...>::v; // table entry of the last pass
-    static_assert(NB * C == NT, "one first- and last-pass butterfly per thread");
-    static_assert(R0 * RadixProd<Rm...>::v * R0 == N, "plan length");
     extern __shared__ float2 lds[];
-    float2* buf0 = lds;
-    float2* buf1 = lds + SL;
-    float2* tp = buf1 + SL;   // pass-major twiddles
+    using Fft = StaticFft<N, C, NT, R0, Rm...>;
+    constexpr int NB = Fft::NB;
     const int lin = xcd_tile(blockIdx.x, gridDim.x);
     const int tile = lin / batch, item = lin - tile * batch;
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
-    const int tid = threadIdx.x;
-    build_pm_direct(tp, plan, tid, NT);
-    const int f0 = tile * C, s = tid % C, j = tid / C;
+    Fft fx(lds, plan, threadIdx.x);
+    const int j = fx.j, s = fx.s, f0 = tile * C;
     const int f = min(f0 + s, F - 1);
     const bool f_ok = f0 + s < F;
-    const int e0 = j * R0 * C + s;        // first-pass outputs j R0 + r
-    const int i1 = j * C + s;             // last-pass inputs j + NB r
-    const int li1 = lidx<1>(i1);
     float2 v[R0], rr[R0], acc[R0];
 #pragma unroll
     for (int r = 0; r < R0; ++r) acc[r] = make_float2(0.f, 0.f);
@@ -798,29 +849,6 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
             rr[r] = Rk[(int64_t)p * F + f];
         }
     };
-    // With an even number of passes the last pass reads the buffer the
-    // first pass writes, so successive transforms start on alternate buffers
-    // (the first pass of one then never overwrites what the last pass of the
-    // previous one may still be reading).
-    int par = 0;
-    auto fft = [&](float2 (&x)[R0], bool inv) {
-        float2* a = (P % 2 == 0 && par) ? buf1 : buf0;
-        float2* b = (P % 2 == 0 && par) ? buf0 : buf1;
-        par ^= 1;
-        dft_small<R0>(x, inv);
-#pragma unroll
-        for (int r = 0; r < R0; ++r) a[lidx<1>(e0 + r * C)] = x[r];
-        lds_barrier();
-        static_mid<N, C, NT, R0, R0 - 1>(RadixList<Rm...>{}, a, b, tp, tid, inv);
-        const float2* tl = tp + TL;   // a holds the last pass's inputs
-#pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            float2 y = a[(NB * C) % 32 == 0 ? li1 + r * (NB * C + NB * C / 32) : lidx<1>(i1 + r * NB * C)];
-            if (r > 0) y = inv ? cmulc(y, tl[j * (R0 - 1) + r - 1]) : cmul(y, tl[j * (R0 - 1) + r - 1]);
-            x[r] = y;
-        }
-        dft_small<R0>(x, inv);
-    };
     gather_s(0);
     gather_r(0);
     for (int k = 0; k < n_imp; ++k) {
@@ -831,7 +859,7 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
             x[r] = ok ? v[r] : make_float2(0.f, 0.f);
         }
         if (k + 1 < n_imp) gather_s(k + 1);
-        fft(x, false);
+        fx.run(x, false);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             acc[r].x += x[r].x * rr[r].x - x[r].y * rr[r].y;
@@ -839,7 +867,7 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
         }
         if (k + 1 < n_imp) gather_r(k + 1);
     }
-    fft(acc, true);
+    fx.run(acc, true);
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
         const int p = j + NB * r;
@@ -851,7 +879,7 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
 static bool plan_is_888(const FftPlan& plan) {
     return plan.n == 512 && plan.npass == 3 && plan.radix[0] == 8 && plan.radix[1] == 8 && plan.radix[2] == 8;
 }
-static size_t static_lds_bytes(const FftPlan& plan, int C) {
+static size_t static_lds_bytes(const FftPlan& plan, int C) {   // as StaticFft::lds_bytes
     return (size_t)(2 * (plan.n * C + plan.n * C / 32) + pm_entries(plan)) * sizeof(float2);
 }
 
@@ -1055,6 +1083,180 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint(
     }
 }
 
+// k_wire_adjoint with a compile-time plan (StaticFft): thread (j, s) holds
+// the wires / wire frequencies j + (N / R0) r of column s throughout, so
+// Gh, each offset's grid-spectrum transform and their products never leave
+// registers, and the next offset's rows are requested before this offset's
+// transforms.
+template <int N, int C, int NT, int R0, int... Rm>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_wire_adjoint_static(const float2* __restrict__ Gt, int64_t ldG, const float2* S, int64_t ldS, float2* O,
+                           int64_t ldO, int n_wires, int n_imp, int F, int nyq, FftPlan plan,
+                           const float2* __restrict__ R, float2* __restrict__ dR, int want_grid, float resp_scale,
+                           int accumulate) {
+    extern __shared__ float2 lds[];
+    using Fft = StaticFft<N, C, NT, R0, Rm...>;
+    constexpr int NB = Fft::NB;
+    Fft fx(lds, plan, threadIdx.x);
+    const int j = fx.j, s = fx.s, f0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const int f = min(f0 + s, F - 1);
+    const bool f_ok = f0 + s < F;
+    const float cf = (f0 + s == 0 || f0 + s == nyq) ? resp_scale : 2.f * resp_scale;
+    float2 gh[R0], v[R0], rr[R0];
+    // unconditional gathers (clamped rows, masked at use), as in k_wire_static
+    auto gather = [&](float2 (&x)[R0], const float2* base, int64_t ld, int rstride, int off) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int p = j + NB * r;
+            asm volatile("" : "+v"(p));
+            x[r] = base[(int64_t)(min(p, n_wires - 1) * rstride + off) * ld + f];
+        }
+    };
+    auto masked = [&](float2 (&x)[R0], const float2 (&y)[R0]) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) x[r] = (f_ok && j + NB * r < n_wires) ? y[r] : make_float2(0.f, 0.f);
+    };
+    auto gather_r = [&](int k) {
+        const float2* Rk = R + (int64_t)k * N * F;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int p = j + NB * r;
+            asm volatile("" : "+v"(p));
+            rr[r] = Rk[(int64_t)p * F + f];
+        }
+    };
+    gather(v, Gt, ldG, 1, 0);
+    masked(gh, v);
+    if (dR) gather(v, S, ldS, n_imp, 0);
+    if (want_grid) gather_r(0);
+    fx.run(gh, false);
+    for (int k = 0; k < n_imp; ++k) {
+        if (dR) {
+            float2 x[R0];
+            masked(x, v);
+            if (k + 1 < n_imp) gather(v, S, ldS, n_imp, k + 1);
+            fx.run(x, false);
+            float2* dRk = dR + (int64_t)k * N * F;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                if (f_ok) {
+                    float2* o = dRk + (int64_t)(j + NB * r) * F + f0 + s;
+                    const float2 g = cmulc(gh[r], x[r]);   // Gh conj(Sk)
+                    float2 cur = accumulate ? *o : make_float2(0.f, 0.f);
+                    cur.x += cf * g.x;
+                    cur.y += cf * g.y;
+                    *o = cur;
+                }
+            }
+        }
+        if (want_grid) {
+            float2 y[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) y[r] = cmulc(gh[r], rr[r]);   // conj(R) Gh
+            if (k + 1 < n_imp) gather_r(k + 1);
+            fx.run(y, true);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int p = j + NB * r;
+                if (p < n_wires && f_ok) O[(int64_t)(p * n_imp + k) * ldO + f0 + s] = y[r];
+            }
+        }
+    }
+}
+
+// k_wire_adjoint_items with a compile-time plan (StaticFft); the next item's
+// Gt rows are requested before this item's transforms, its grid-spectrum
+// rows right before the transform of Gh.
+template <int N, int C, int NT, int R0, int... Rm>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_wire_adjoint_items_static(const float2* __restrict__ Gt, int64_t ldG, int64_t strideG, float2* S,
+                                 int64_t ldS, int64_t strideS, int batch, int groups, int n_wires, int n_imp,
+                                 int F, int nyq, FftPlan plan, const float2* __restrict__ R,
+                                 float2* __restrict__ dR, float2* __restrict__ part, int64_t part_stride,
+                                 float resp_scale, int accumulate) {
+    extern __shared__ float2 lds[];
+    using Fft = StaticFft<N, C, NT, R0, Rm...>;
+    constexpr int NB = Fft::NB;
+    Fft fx(lds, plan, threadIdx.x);
+    const int lin = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = lin / groups, grp = lin - tile * groups;
+    const int per = (batch + groups - 1) / groups;
+    const int b0 = grp * per, b1 = min(batch, b0 + per);
+    if (groups > 1 && dR) {
+        dR = part + (int64_t)grp * part_stride;
+        accumulate = 0;
+    }
+    const int j = fx.j, s = fx.s, f0 = tile * C;
+    const int f = min(f0 + s, F - 1);
+    const bool f_ok = f0 + s < F;
+    const float cf = (f0 + s == 0 || f0 + s == nyq) ? resp_scale : 2.f * resp_scale;
+    auto gather = [&](float2 (&x)[R0], const float2* base, int64_t ld, int rstride, int off) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int p = j + NB * r;
+            asm volatile("" : "+v"(p));
+            x[r] = base[(int64_t)(min(p, n_wires - 1) * rstride + off) * ld + f];
+        }
+    };
+    auto masked = [&](float2 (&x)[R0]) {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) x[r] = (f_ok && j + NB * r < n_wires) ? x[r] : make_float2(0.f, 0.f);
+    };
+    for (int k = 0; k < n_imp; ++k) {
+        float2 dacc[R0], rr[R0], g[R0];
+        const float2* Rk = R + (int64_t)k * N * F;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            dacc[r] = make_float2(0.f, 0.f);
+            int p = j + NB * r;
+            asm volatile("" : "+v"(p));
+            rr[r] = Rk[(int64_t)p * F + f];
+        }
+        if (b0 < b1) gather(g, Gt + (int64_t)b0 * strideG, ldG, 1, 0);
+        for (int b = b0; b < b1; ++b) {
+            float2* Sb = S + (int64_t)b * strideS;
+            float2 gh[R0], x[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) gh[r] = g[r];
+            masked(gh);
+            if (dR) gather(x, Sb, ldS, n_imp, k);
+            if (b + 1 < b1) gather(g, Gt + (int64_t)(b + 1) * strideG, ldG, 1, 0);
+            fx.run(gh, false);
+            if (dR) {
+                masked(x);
+                fx.run(x, false);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const float2 q = cmulc(gh[r], x[r]);   // Gh conj(Sk)
+                    dacc[r].x += q.x;
+                    dacc[r].y += q.y;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R0; ++r) x[r] = cmulc(gh[r], rr[r]);   // conj(R) Gh
+            fx.run(x, true);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int p = j + NB * r;
+                if (p < n_wires && f_ok) Sb[(int64_t)(p * n_imp + k) * ldS + f0 + s] = x[r];
+            }
+        }
+        if (dR) {
+            float2* dRk = dR + (int64_t)k * N * F;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                if (f_ok) {
+                    float2* o = dRk + (int64_t)(j + NB * r) * F + f0 + s;
+                    float2 cur = accumulate ? *o : make_float2(0.f, 0.f);
+                    cur.x += cf * dacc[r].x;
+                    cur.y += cf * dacc[r].y;
+                    *o = cur;
+                }
+            }
+        }
+    }
+}
+
 template <int VPT, int C, int NT>
 static hipError_t wire_adj_launch(const float2* Gt, int64_t ldG, const float2* S, int64_t ldS,
                                   float2* O, int64_t ldO, int n_wires, int n_imp, int F, int nyq,
@@ -1076,6 +1278,15 @@ hipError_t launch_wire_adjoint(const float2* Gt, int64_t ldG, const float2* S, i
     FftPlan plan;
     if (!make_plan(nw_fft, &plan)) return hipErrorInvalidValue;
     const int F = nt_fft / 2 + 1, nyq = nt_fft / 2;
+    if (plan_is_888(plan)) {   // 16 columns x 1024 threads, as the forward pass's default
+        constexpr int C = 16;
+        auto kern = k_wire_adjoint_static<512, C, 64 * C, 8, 8>;
+        const size_t lds = static_lds_bytes(plan, C);
+        set_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3((F + C - 1) / C), dim3(64 * C), lds, s, Gt, ldG, S, ldS, O, ldO, n_wires,
+                           n_imp, F, nyq, plan, R, dR, want_grid ? 1 : 0, resp_scale, accumulate ? 1 : 0);
+        return hipGetLastError();
+    }
 #define LAR_WADJ(V)                                                                                   \
     return wire_adj_launch<V, 8, 512>(Gt, ldG, S, ldS, O, ldO, n_wires, n_imp, F, nyq, plan, R, dR,   \
                                       want_grid, resp_scale, accumulate, s);
@@ -1244,9 +1455,17 @@ hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t stri
     const int64_t pstride = (int64_t)n_imp * nw_fft * F;
     float2* part = reinterpret_cast<float2*>(scratch);
     constexpr int C = 8;
-    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
     dim3 grid((unsigned)(((F + C - 1) / C) * groups));
     hipError_t e = hipErrorInvalidValue;
+    if (plan_is_888(plan)) {
+        auto kern = k_wire_adjoint_items_static<512, C, 64 * C, 8, 8>;
+        const size_t lds8 = static_lds_bytes(plan, C);
+        set_lds(kern, lds8);
+        hipLaunchKernelGGL(kern, grid, dim3(64 * C), lds8, s, Gt, ldG, strideG, S, ldS, strideS, batch, groups,
+                           n_wires, n_imp, F, nyq, plan, R, dR, part, pstride, resp_scale, accumulate ? 1 : 0);
+        e = hipGetLastError();
+    }
+    const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
 #define LAR_WADJI(V, NT)                                                                                \
     {                                                                                                   \
         set_lds(k_wire_adjoint_items<V, C, NT>, lds);                                                   \
@@ -1255,7 +1474,8 @@ hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t stri
                            pstride, resp_scale, accumulate ? 1 : 0);                                    \
         e = hipGetLastError();                                                                          \
     }
-    if (nw_fft <= 128) LAR_WADJI(2, 512)
+    if (plan_is_888(plan)) {
+    } else if (nw_fft <= 128) LAR_WADJI(2, 512)
     else if (nw_fft <= 256) LAR_WADJI(4, 512)
     else if (nw_fft <= 512) LAR_WADJI(8, 512)
     else if (nw_fft <= 1024) LAR_WADJI(8, 1024)
