@@ -159,6 +159,25 @@ def tune_plane(args, P):
     log(f"bench: schedule {key} {json.dumps(TUNED[key])}")
 
 
+def tune_raster(args, P, D, fl):
+    """Time the raster tiles of this plane shape on these depositions and
+    register the fastest (outside every timed region)."""
+    from paper_2203_02479_amd import autotune
+    key = autotune.shape_key(P)
+    if args.no_tune or TUNED.get(key, {}).get("raster_ms"):
+        return
+    out = autotune.tune_raster(P, D, inputs_mod().NSIGMA, fl, reps=5, cache=False)
+    entry = TUNED.setdefault(key, {})
+    entry["raster_tile"] = out["raster_tile"]
+    entry["raster_ms"] = {str(k): round(v, 4) for k, v in out["ms"].items()}
+    log(f"bench: raster tile {key} {json.dumps(entry['raster_ms'])} -> {out['raster_tile']}")
+
+
+def inputs_mod():
+    from paper_2203_02479_amd import inputs
+    return inputs
+
+
 def fft_roofline(nbytes, per):
     out = {}
     for k in ("r2c", "wire", "c2r", "fill"):
@@ -180,6 +199,7 @@ def leg_forward(args, torch, lar, inputs, np, mode, K, warmup, with_stages=True)
     tune_plane(args, P)
     seed = inputs.SEED0 + 100
     fl0 = (mode, seed, 0, 2) if mode else None
+    tune_raster(args, P, D, (1, seed, 0, 2))   # the tile of the headline (binomial) workload
     ws = lar.workspace(lar.sim_plane_workspace(P, len(dep), fl0))
     wave = torch.empty((P.n_wires, P.n_ticks), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -233,6 +253,7 @@ def leg_three_plane(args, torch, lar, inputs, np):
         tune_plane(args, p)
     Ds = [lar.DeviceDepos.from_host(d) for d in ev.depos]
     fl = (1, seed, 0, 0)
+    tune_raster(args, planes[0], Ds[0], fl)
     wss = [lar.workspace(lar.sim_plane_workspace(p, len(d), fl)) for p, d in zip(planes, ev.depos)]
     waves = [torch.empty((p.n_wires, p.n_ticks), device="cuda") for p in planes]
     n_depo = len(ev.depos[0])

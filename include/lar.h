@@ -389,8 +389,8 @@ int lar_sim_streams(const lar_plane *planes, int32_t n_types, const float *const
                     int32_t n_streams, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- schedules
- * Launch schedule of the FFT convolution for one plane shape (no paper
- * counterpart: a tuning knob of this implementation).  Every valid schedule
+ * Launch schedule of the FFT convolution and of the raster for one plane
+ * shape (no paper counterpart: a tuning knob of this implementation).  Every valid schedule
  * computes the same transform up to float rounding; which one is fastest
  * depends on the shape.  Schedules are keyed by (n_wires, n_imp, n_ticks,
  * nt_fft, nw_fft), process-wide, and read when a call launches its kernels
@@ -406,7 +406,11 @@ typedef struct lar_schedule {
     int32_t wire_threads;   /* threads per wire-pass workgroup: 256, 512, 1024
                                (cols 4: 256/512; cols 16: 512/1024) */
     int32_t wire_order;     /* radix order of the nw_fft-point plan */
-    int32_t reserved;       /* 0 */
+    int32_t raster_tile;    /* floats of a raster wave's LDS tile: 384, 512, 640, 768
+                               (0 in lar_schedule_set: the built-in 512).  A wave sums
+                               the patches of its 16 depos there when their bounding
+                               box fits, else adds them straight to the grid; larger
+                               tiles take more LDS per workgroup */
 } lar_schedule;
 
 /* The built-in schedule of a shape / the one in effect (registered or
@@ -422,8 +426,8 @@ int lar_schedule_get(const lar_plane *plane, lar_schedule *out);
 int lar_schedule_set(const lar_plane *plane, const lar_schedule *sched);
 /* Valid schedules to time: the built-in one first, then every other row
  * choice with the built-in wire pass, then every other wire choice with the
- * built-in rows (radix orders that
- * repeat an earlier order's plan are left out).  Writes up to cap entries
+ * built-in rows (radix orders that repeat an earlier order's plan are left
+ * out), then every other raster tile with the built-in FFT choices.  Writes up to cap entries
  * and sets *n to the full count. */
 int lar_schedule_candidates(const lar_plane *plane, lar_schedule *out, int32_t cap, int32_t *n);
 

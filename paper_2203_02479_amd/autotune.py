@@ -1,4 +1,5 @@
-"""Timing-based choice of FFT-convolution launch schedules, with a JSON cache.
+"""Timing-based choice of FFT-convolution and raster launch schedules, with a
+JSON cache.
 
 For one plane shape, every candidate schedule of the C library
 (``lar_schedule_candidates``) runs ``lar_fftconv`` on the same synthetic
@@ -9,6 +10,13 @@ the spectrum buffers), so the best row choice and the best wire choice are
 combined and registered with ``lar_schedule_set``.  A candidate whose
 waveforms differ from the built-in schedule's by more than float rounding
 (relative L2 above 1e-5) is rejected.
+
+The raster's per-wave LDS tile (``raster_tile``) is chosen apart by
+``tune_raster``, on the caller's depositions: which size is fastest depends
+on how many sub-chunks' bounding boxes fit it, so on the depo widths and
+spacing as well as on the shape.  Every tile gives the same fluctuated
+counts (bit for bit) and the same mean patches up to float rounding; a tile
+whose grid differs from the built-in tile's beyond that is rejected.
 
 The cache maps ``arch -> shape key -> schedule`` and lives at
 ``$LAR_TUNE_CACHE`` or ``~/.cache/lar_sim/schedules.json``.
@@ -25,6 +33,7 @@ from . import lar
 
 ROW_KEYS = ("row_threads", "row_order")
 WIRE_KEYS = ("wire_cols", "wire_threads", "wire_order")
+FFT_KEYS = ROW_KEYS + WIRE_KEYS
 
 
 def cache_path() -> str:
@@ -104,6 +113,8 @@ def tune(plane, device="cuda", reps=10, warmup=2, seed=1234, apply=True, cache=T
     ref = None
     try:
         for cand in lar.schedule_candidates(plane):
+            if cand["raster_tile"] != default["raster_tile"]:   # raster choices: tune_raster
+                continue
             lar.schedule_set(plane, cand)
             for _ in range(warmup):
                 lar.fftconv(plane, grid, resp, wave, ws, stream)
@@ -131,7 +142,7 @@ def tune(plane, device="cuda", reps=10, warmup=2, seed=1234, apply=True, cache=T
     wire_c = [r for r in results if same(r[0], default, ROW_KEYS)]
     best_row = min(row_c, key=lambda r: r[1])
     best_wire = min(wire_c, key=lambda r: r[2])
-    best = dict(default)
+    best = dict(previous)         # keeps a raster tile tuned before
     best.update({k: best_row[0][k] for k in ROW_KEYS})
     best.update({k: best_wire[0][k] for k in WIRE_KEYS})
     d_row = next(r for r in results if r[0] == default)
@@ -149,6 +160,62 @@ def tune(plane, device="cuda", reps=10, warmup=2, seed=1234, apply=True, cache=T
             "schedule": best, "ms": best_row[1] + best_wire[2]}
         _write(path, data)
     return out
+
+
+def tune_raster(plane, depos, nsigma, fluct, device="cuda", reps=5, warmup=2, apply=True, cache=True,
+                verbose=False) -> dict:
+    """Time lar_raster over these device depositions (lar.DeviceDepos) for
+    every raster tile of this plane shape's candidates, the FFT choices
+    held at the schedule in effect, and return {"raster_tile": best,
+    "ms": {tile: median ms}}.  With apply, the best tile is registered;
+    with cache, stored with the shape's schedule under this device's arch."""
+    dev = torch.device(device)
+    stream = torch.cuda.current_stream(dev)
+    current = lar.schedule_get(plane)
+    default = lar.schedule_default(plane)
+    tiles = sorted({c["raster_tile"] for c in lar.schedule_candidates(plane)})
+    grid = torch.zeros((plane.n_wires * plane.n_imp, plane.n_ticks), dtype=torch.float32, device=dev)
+    ws = lar.workspace(lar.raster_workspace(plane, len(depos), fluct), dev)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times, ref = {}, None
+    try:
+        for tile in [default["raster_tile"]] + [t for t in tiles if t != default["raster_tile"]]:
+            lar.schedule_set(plane, dict(current, raster_tile=tile))
+            samples = []
+            for i in range(warmup + reps):
+                grid.zero_()
+                start.record(stream)
+                lar.raster(plane, depos, nsigma, fluct, grid, ws, stream)
+                end.record(stream)
+                stream.synchronize()
+                if i >= warmup:
+                    samples.append(start.elapsed_time(end))
+            if ref is None:           # the built-in tile first
+                ref = grid.clone()
+                ref_norm = max(float(torch.linalg.vector_norm(ref)), 1e-30)
+            else:
+                exact = fluct is not None and fluct[0] != 0
+                err = float(torch.linalg.vector_norm(grid - ref)) / ref_norm
+                if (exact and not torch.equal(grid, ref)) or err > 1e-6:
+                    if verbose:
+                        print(f"[autotune] {shape_key(plane)} rejects raster tile {tile}: rel err {err:.2e}",
+                              flush=True)
+                    continue
+            times[tile] = statistics.median(samples)
+    finally:
+        lar.schedule_set(plane, current if current != default else None)
+    best = min(times, key=times.get)
+    if verbose:
+        print(f"[autotune] {shape_key(plane)} raster tiles {times} -> {best}", flush=True)
+    if apply:
+        lar.schedule_set(plane, dict(current, raster_tile=best))
+    if cache:
+        path = cache_path()
+        data = _read(path)
+        entry = data.setdefault(device_arch(dev), {}).setdefault(shape_key(plane), {"schedule": current})
+        entry["schedule"] = dict(entry["schedule"], raster_tile=best)
+        _write(path, data)
+    return {"raster_tile": best, "ms": times}
 
 
 def load(planes, device="cuda", path=None) -> int:

@@ -426,7 +426,8 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         b->steps.push_back([=](hipStream_t s) { return launch_fill(g, gstride * k, s); });
         if (w.total_sub > 0)
             b->steps.push_back([=](hipStream_t s) {
-                return launch_raster_items(mode, one, wtab, k, w.total_sub, rws, rws_bytes, s);
+                return launch_raster_items(mode, one, wtab, k, w.total_sub, rws, rws_bytes, s, nullptr,
+                                           sc.raster_tile);
             });
         // grids of a wave are gstride floats apart: one launch when unpadded
         if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
@@ -552,7 +553,8 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
             LAR_BTRY(launch_fill(g, gstride * k, s));
             if (w.total_sub > 0) {
                 const RasterItem one{};
-                LAR_BTRY(launch_raster_items(0, one, b->dtab + w.first, k, w.total_sub, nullptr, 0, s));
+                LAR_BTRY(launch_raster_items(0, one, b->dtab + w.first, k, w.total_sub, nullptr, 0, s, nullptr,
+                                             sc.raster_tile));
             }
             if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
                 LAR_BTRY(launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s, sc.row_threads,

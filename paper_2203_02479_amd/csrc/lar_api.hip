@@ -151,7 +151,7 @@ static int raster_impl(const lar_plane* plane, const lar_depos* depos, float nsi
     a.plane = fluct ? fluct->plane : 0u;
     a.seed = fluct ? fluct->seed : 0ull;
     LAR_TRY(launch_raster(a, depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x,
-                          depos->n, grid, ws, ws_bytes, stream, g_stage_ev[1]));
+                          depos->n, grid, ws, ws_bytes, stream, g_stage_ev[1], sched_of(plane).raster_tile));
     LAR_TRY(stage_mark(2, stream));
     return LAR_OK;
 }

@@ -408,7 +408,10 @@ int device_cus();   // compute units of the current device (cached)
 struct Sched {
     int row_threads, row_order;
     int wire_cols, wire_threads, wire_order;
+    int raster_tile;   // floats of a raster wave's private LDS tile
 };
+constexpr int kRasterTileDefault = 512;
+bool raster_tile_ok(int tile);   // 384, 512, 640 or 768
 int default_row_threads(int nt_fft);
 int default_wire_cols(int nw_fft);
 int default_wire_threads(int nw_fft);
@@ -469,11 +472,14 @@ constexpr size_t kDeferredBytes = 16;
 // main_done (optional): recorded on s right after the main raster kernel.
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,
-                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done = nullptr);
+                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done = nullptr,
+                         int tile = kRasterTileDefault);
 // items: device table (n_items entries) or nullptr with `one` used alone.
+// tile: floats of a wave's LDS tile (raster_tile_ok; the sub-chunks whose
+// bounding box exceeds it add straight to the grid).
 hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
                                int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s,
-                               hipEvent_t main_done = nullptr);
+                               hipEvent_t main_done = nullptr, int tile = kRasterTileDefault);
 hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);

@@ -811,7 +811,6 @@ static constexpr int kSub = kRasterSub;   // depos per wave sub-chunk
 static constexpr int kMaxT = 16;          // window limits of the LDS slots (bins)
 static constexpr int kMaxX = 32;
 static constexpr int kSlot = kMaxT + kMaxX + 1;
-static constexpr int kWaveTile = 512;     // floats of a wave's private tile
 static constexpr int kWaveQueue = 256;    // deferred bins buffered per wave
 // k_raster's grid is capped at this many workgroups per CU; below the cap
 // every wave takes one sub-chunk and the workgroup dispatcher balances the
@@ -929,14 +928,14 @@ __device__ __forceinline__ bool queue_write(DeferredBin* queue, int part, unsign
 
 // 5 waves per SIMD: the sampler stages fit 96 VGPRs, and the LDS of a
 // workgroup (about 29 KB) lets 5 workgroups share a CU
-template <int MODE>
+template <int MODE, int TILE>
 __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(5, 8)))
 void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items, int64_t total_sub,
               RasterWs* __restrict__ ws, uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue,
               unsigned long long cap) {
     constexpr bool FLUCT = MODE != 0;
     __shared__ float s_w[kWaves][kSub * kSlot];
-    __shared__ float s_tile[kWaves][kWaveTile];
+    __shared__ float s_tile[kWaves][TILE];
     __shared__ int s_meta[kWaves][4][kSub];            // jlo, nt, mlo, nx (nt<0 / nx<0: point axis)
     __shared__ float s_q[kWaves][kSub];
     __shared__ int s_off[kWaves][FLUCT ? kSub + 1 : 1];
@@ -952,7 +951,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
     int* mlo_ = s_meta[wv][2];
     int* nx_ = s_meta[wv][3];
     float* q_ = s_q[wv];
-    for (int i = lane; i < kWaveTile; i += 64) tile[i] = 0.f;
+    for (int i = lane; i < TILE; i += 64) tile[i] = 0.f;
     if (FLUCT) {
         for (int i = threadIdx.x; i < kRcpTable; i += kRasterThreads) s_rcp[i] = i ? 1.0 / (double)i : 0.0;
         __syncthreads();
@@ -1009,7 +1008,7 @@ void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items,
             continue;
         }
         const int span_t = jmax - jmin + 1, span_x = mmax - mmin + 1;
-        const bool use_tile = span_t * span_x <= kWaveTile;
+        const bool use_tile = span_t * span_x <= TILE;
         if (FLUCT) {   // exclusive prefix of cell counts over the sub-chunk (scalar)
             int acc = 0, mine = 0;
 #pragma unroll
@@ -1677,10 +1676,22 @@ hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t
     return hipGetLastError();
 }
 
+bool raster_tile_ok(int tile) { return tile == 384 || tile == 512 || tile == 640 || tile == 768; }
+
+// X(T) with the compile-time tile T of a raster_tile_ok value
+#define LAR_TILE_DISPATCH(tile, X)  \
+    switch (tile) {                 \
+        case 384: X(384) break;     \
+        case 640: X(640) break;     \
+        case 768: X(768) break;     \
+        default: X(512) break;      \
+    }
+
 hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
                                int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s,
-                               hipEvent_t main_done) {
+                               hipEvent_t main_done, int tile) {
     if (total_sub <= 0) return hipSuccess;
+    if (!raster_tile_ok(tile)) return hipErrorInvalidValue;
     const int64_t cap_blocks = 8 * (int64_t)device_cus();
     const int64_t dgrid = kDeferredGroupsPerCU * (int64_t)device_cus();
     const int64_t nblk = (total_sub + kWaves - 1) / kWaves;
@@ -1689,8 +1700,11 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     const int64_t nwide = (total_sub + (kRasterThreads / kSub) - 1) / (kRasterThreads / kSub);
     dim3 gw((unsigned)(nwide < cap_blocks ? nwide : cap_blocks));
     if (mode == 0) {
-        hipLaunchKernelGGL(k_raster<0>, grd, blk, 0, s, one, items, n_items, total_sub, nullptr, nullptr,
-                           nullptr, 0ull);
+#define LAR_MEAN(T)                                                                                     \
+    hipLaunchKernelGGL((k_raster<0, T>), grd, blk, 0, s, one, items, n_items, total_sub, nullptr, nullptr, \
+                       nullptr, 0ull);
+        LAR_TILE_DISPATCH(tile, LAR_MEAN)
+#undef LAR_MEAN
         if (main_done) (void)hipEventRecord(main_done, s);
         hipLaunchKernelGGL(k_raster_wide, gw, blk, 0, s, one, items, n_items, total_sub);
         return hipGetLastError();
@@ -1705,9 +1719,10 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
     const int64_t rblk = (total_sub + 255) / 256;
     const dim3 g256((unsigned)(rblk < cap_blocks ? rblk : cap_blocks));   // 256 sub-chunks per block
     hipLaunchKernelGGL(k_raster_reset, g256, dim3(256), 0, s, hdr, flags, total_sub);
+#define LAR_MAIN(T) \
+    hipLaunchKernelGGL((k_raster<LAR_M, T>), grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, cap);
 #define LAR_FLUCT(M)                                                                                 \
-    hipLaunchKernelGGL(k_raster<M>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, \
-                       cap);                                                                         \
+    LAR_TILE_DISPATCH(tile, LAR_MAIN)                                                                \
     if (main_done) (void)hipEventRecord(main_done, s);                                               \
     hipLaunchKernelGGL(k_raster_deferred<M>, dim3((unsigned)dgrid), dim3(kDefWaves * 64), 0, s,       \
                        one, items, hdr, flags, queue, cap);                                          \
@@ -1715,23 +1730,31 @@ hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem
                        items, hdr, flags, queue, cap);                                               \
     hipLaunchKernelGGL(k_raster_flagged<M>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     if (mode == 1) {
+#define LAR_M 1
         LAR_FLUCT(1)
+#undef LAR_M
     } else if (mode == 2) {
+#define LAR_M 2
         LAR_FLUCT(2)
+#undef LAR_M
     } else {
         // normal approximation: no queued draws, only depos wider than the
         // weight slots are flagged
-        hipLaunchKernelGGL(k_raster<3>, grd, blk, 0, s, one, items, n_items, total_sub, hdr, flags, queue, cap);
+#define LAR_M 3
+        LAR_TILE_DISPATCH(tile, LAR_MAIN)
+#undef LAR_M
         if (main_done) (void)hipEventRecord(main_done, s);
         hipLaunchKernelGGL(k_raster_flagged<3>, g256, dim3(256), 0, s, one, items, n_items, total_sub, flags);
     }
 #undef LAR_FLUCT
+#undef LAR_MAIN
     return hipGetLastError();
 }
+#undef LAR_TILE_DISPATCH
 
 hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, const float* x,
                          const float* st, const float* sx, int64_t n, float* grid, void* ws,
-                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done) {
+                         size_t ws_bytes, hipStream_t s, hipEvent_t main_done, int tile) {
     if (n <= 0) return hipSuccess;
     RasterItem one;
     one.A = a;
@@ -1739,7 +1762,7 @@ hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, co
     one.grid = grid;
     one.n = n;
     one.sub_begin = 0;
-    return launch_raster_items(a.mode, one, nullptr, 1, raster_subchunks(n), ws, ws_bytes, s, main_done);
+    return launch_raster_items(a.mode, one, nullptr, 1, raster_subchunks(n), ws, ws_bytes, s, main_done, tile);
 }
 
 }  // namespace lar

@@ -1,8 +1,9 @@
 // schedule.hip -- per-shape launch schedules of the FFT convolution.
 //
 // A schedule picks, for one plane shape, the workgroup size and radix order
-// of the time-axis row transforms and the tile width, workgroup size and
-// radix order of the fused wire pass.  Every choice gives the same
+// of the time-axis row transforms, the tile width, workgroup size and
+// radix order of the fused wire pass, and the size of the raster's per-wave
+// LDS tile.  Every choice gives the same
 // transform up to rounding; the fastest one depends on the shape and is
 // found by timing (the Python autotuner), then registered here.  Lookups
 // happen when a call launches its kernels (a batch plan reads them when it
@@ -31,6 +32,7 @@ Sched sched_default(int nt_fft, int nw_fft) {
     s.wire_cols = default_wire_cols(nw_fft);
     s.wire_threads = default_wire_threads(nw_fft);
     s.wire_order = 0;
+    s.raster_tile = kRasterTileDefault;
     return s;
 }
 
@@ -50,7 +52,7 @@ bool order_repeats(int n, int o) {
 
 bool sched_ok(const Sched& s, int nt_fft, int nw_fft) {
     return row_sched_ok(nt_fft, s.row_threads, s.row_order) &&
-           wire_sched_ok(nw_fft, s.wire_cols, s.wire_threads, s.wire_order);
+           wire_sched_ok(nw_fft, s.wire_cols, s.wire_threads, s.wire_order) && raster_tile_ok(s.raster_tile);
 }
 }  // namespace
 
@@ -83,6 +85,7 @@ static Sched from_abi(const lar_schedule* s) {
     r.wire_cols = s->wire_cols;
     r.wire_threads = s->wire_threads;
     r.wire_order = s->wire_order;
+    r.raster_tile = s->raster_tile ? s->raster_tile : kRasterTileDefault;
     return r;
 }
 
@@ -92,7 +95,7 @@ static void to_abi(const Sched& s, lar_schedule* r) {
     r->wire_cols = s.wire_cols;
     r->wire_threads = s.wire_threads;
     r->wire_order = s.wire_order;
-    r->reserved = 0;
+    r->raster_tile = s.raster_tile;
 }
 
 extern "C" {
@@ -140,7 +143,7 @@ int lar_schedule_candidates(const lar_plane* p, lar_schedule* out, int32_t cap, 
     auto same = [](const Sched& a, const Sched& b) {
         return a.row_threads == b.row_threads && a.row_order == b.row_order &&
                a.wire_cols == b.wire_cols && a.wire_threads == b.wire_threads &&
-               a.wire_order == b.wire_order;
+               a.wire_order == b.wire_order && a.raster_tile == b.raster_tile;
     };
     auto emit = [&](const Sched& s) {
         if (!sched_ok(s, p->nt_fft, p->nw_fft)) return;
@@ -170,6 +173,12 @@ int lar_schedule_candidates(const lar_plane* p, lar_schedule* out, int32_t cap, 
                 s.wire_order = o;
                 if (!same(s, d)) emit(s);
             }
+    // raster tiles with the default FFT choices
+    for (int t : {384, 640, 768}) {
+        Sched s = d;
+        s.raster_tile = t;
+        if (!same(s, d)) emit(s);
+    }
     *n = count;
     return LAR_OK;
 }

@@ -59,9 +59,9 @@ class lar_plane_proj(ctypes.Structure):
 
 class lar_schedule(ctypes.Structure):
     _fields_ = [("row_threads", ctypes.c_int32), ("row_order", ctypes.c_int32), ("wire_cols", ctypes.c_int32),
-                ("wire_threads", ctypes.c_int32), ("wire_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wire_threads", ctypes.c_int32), ("wire_order", ctypes.c_int32), ("raster_tile", ctypes.c_int32)]
 
-    FIELDS = ("row_threads", "row_order", "wire_cols", "wire_threads", "wire_order")
+    FIELDS = ("row_threads", "row_order", "wire_cols", "wire_threads", "wire_order", "raster_tile")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k in self.FIELDS}
@@ -426,7 +426,7 @@ def schedule_set(plane, sched):
     shape; None restores the built-in schedule."""
     ptr = None
     if sched is not None:
-        ptr = ctypes.byref(lar_schedule(*(int(sched[k]) for k in lar_schedule.FIELDS), 0))
+        ptr = ctypes.byref(lar_schedule(*(int(sched.get(k, 0)) for k in lar_schedule.FIELDS)))
     _check(_lib().lar_schedule_set(ctypes.byref(make_plane(plane)), ptr), "lar_schedule_set")
 
 

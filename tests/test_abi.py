@@ -160,11 +160,11 @@ def test_stage_calls_host_side_errors(lar):
 def test_schedule_registry_host_side(lar):
     P = inputs.cfg1_plane()
     d = lar.schedule_default(P)
-    assert d == dict(row_threads=384, row_order=4, wire_cols=16, wire_threads=1024, wire_order=0)
+    assert d == dict(row_threads=384, row_order=4, wire_cols=16, wire_threads=1024, wire_order=0, raster_tile=512)
     assert lar.schedule_get(P) == d
     cands = lar.schedule_candidates(P)
     assert cands[0] == d and len(cands) == len({tuple(c.values()) for c in cands})
-    other = dict(d, wire_cols=16, wire_threads=1024, wire_order=1, row_threads=1024)
+    other = dict(d, wire_cols=16, wire_threads=1024, wire_order=1, row_threads=1024, raster_tile=640)
     lar.schedule_set(P, other)
     try:
         assert lar.schedule_get(P) == other
@@ -177,7 +177,8 @@ def test_schedule_registry_host_side(lar):
     # Tf/2 = 3072 over 256 threads is 12 values per thread; 4 x 1024 is not a
     # wire shape; radix order 5 does not exist; 16 x 512 is 16 values of Wf 512
     for bad in (dict(row_threads=256), dict(wire_cols=4, wire_threads=1024), dict(row_order=5),
-                dict(wire_order=-1), dict(wire_cols=16, wire_threads=512), dict(row_threads=300)):
+                dict(wire_order=-1), dict(wire_cols=16, wire_threads=512), dict(row_threads=300),
+                dict(raster_tile=500), dict(raster_tile=1024)):
         with pytest.raises(lar.LarError) as e:
             lar.schedule_set(P, dict(d, **bad))
         assert e.value.status == lar.LAR_EINVAL
@@ -207,3 +208,5 @@ def test_schedule_candidates_every_shape_valid(lar):
     assert wire_orders == {0, 1}            # 512 = 8^3: orders 2, 3 and 4 repeat order 0
     row_orders = {c["row_order"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
     assert 4 in row_orders                  # 3072 = 8 8 8 6 with a radix-6 pass
+    tiles = {c["raster_tile"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
+    assert tiles == {384, 512, 640, 768}

@@ -84,7 +84,7 @@ def test_batch_under_non_default_schedule():
     P = planes[0]
     resps = [lar.spectrum_from_time(P, inputs.response_time(P.n_imp, P.half_w, 200, P.kind))]
     d = lar.schedule_default(P)
-    alt = dict(d, wire_cols=4, wire_threads=256, row_threads=1024, row_order=1)
+    alt = dict(d, wire_cols=4, wire_threads=256, row_threads=1024, row_order=1, raster_tile=384)
     deps = [inputs.random_depos(P, n, seed=300 + i, margin=0.1) for i, n in enumerate((900, 0, 2500))]
     items, off, woff = [], 0, 0
     for i, dep in enumerate(deps):
@@ -111,5 +111,50 @@ def test_batch_under_non_default_schedule():
                 ref = w.cpu().numpy().reshape(-1)
                 assert rel_l2(got[wo:wo + ref.size], ref) < RTOL_L2
         b.close()
+    finally:
+        lar.schedule_set(P, None)
+
+
+def test_every_raster_tile_matches_oracle(tmp_path, monkeypatch):
+    """Each listed raster tile: the mean grid within the oracle's tolerance,
+    the binomial grid nearly equal to the oracle's and identical bit for bit
+    across tiles (whether a sub-chunk sums in the tile or adds straight to
+    the grid changes no count); tune_raster registers a listed tile."""
+    import torch
+    from paper_2203_02479_amd import autotune, lar
+    monkeypatch.setenv("LAR_TUNE_CACHE", str(tmp_path / "sched.json"))
+    ev = inputs.cfg0_event()
+    P, dep = ev.planes[0], ev.depos[0]
+    dep.sigma_t[::7] *= 2.5          # wider bounding boxes: some sub-chunks exceed the small tiles
+    D = lar.DeviceDepos.from_host(dep)
+    ref_mean = oracle.raster_mean(P, dep, inputs.NSIGMA)
+    fl = (1, 99, 3, 1)
+    ref_fl = oracle.raster_fluct(P, dep, inputs.NSIGMA, mode=1, seed=99, event=3, plane_id=1)
+    grid = torch.zeros((P.n_rows, P.n_ticks), dtype=torch.float32, device="cuda")
+    tiles = sorted({c["raster_tile"] for c in lar.schedule_candidates(P)})
+    assert tiles == [384, 512, 640, 768]
+    first = None
+    try:
+        for tile in tiles:
+            print(f"raster tile {tile}", flush=True)
+            lar.schedule_set(P, dict(lar.schedule_default(P), raster_tile=tile))
+            grid.zero_()
+            lar.raster(P, D, inputs.NSIGMA, None, grid, None)
+            torch.cuda.synchronize()
+            g = grid.cpu().numpy()
+            assert rel_l2(g, ref_mean) < RTOL_L2, tile
+            assert np.max(np.abs(g - ref_mean)) <= 1e-5 * np.max(np.abs(ref_mean)), tile
+            grid.zero_()
+            lar.raster(P, D, inputs.NSIGMA, fl, grid, lar.workspace(lar.raster_workspace(P, len(dep), fl)))
+            torch.cuda.synchronize()
+            g = grid.cpu().numpy()
+            assert np.mean(g == ref_fl) > 0.9999, tile
+            if first is None:
+                first = g
+            assert np.array_equal(g, first), tile
+        lar.schedule_set(P, None)
+        out = autotune.tune_raster(P, D, inputs.NSIGMA, fl, reps=2, warmup=1)
+        assert out["raster_tile"] in tiles and set(out["ms"]) == set(tiles)
+        assert lar.schedule_get(P)["raster_tile"] == out["raster_tile"]
     finally:
         lar.schedule_set(P, None)
