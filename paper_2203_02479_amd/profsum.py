@@ -26,9 +26,9 @@ import sys
 # bench stage -> kernel name pattern of the timed single-plane step
 STAGE_KERNELS = {
     "fill": r"k_fill_zero\b",
-    "raster": r"k_raster<1>|k_raster<2>|k_raster<0>",
+    "raster": r"k_raster<[0-2][,>]",
     "r2c": r"k_r2c_rows",
-    "wire": r"k_wire_fused",
+    "wire": r"k_wire_fused|k_wire_static",
     "c2r": r"k_c2r_rows",
 }
 CALIB_BYTES = 4 * (1 << 28)          # bench.py --calib copies 1 GiB of float32
