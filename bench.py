@@ -523,7 +523,7 @@ def main():
                        "avg_ms": round(t_all, 5)}
     fft_ms = per["r2c"] + per["wire"] + per["c2r"]
     fft_b = nbytes["r2c"] + nbytes["wire"] + nbytes["c2r"]
-    roof_fft_all = {"kernels": "k_r2c_rows + k_wire_fused + k_c2r_rows", "bound": "hbm",
+    roof_fft_all = {"kernels": "k_r2c_rows + k_wire_static + k_c2r_rows", "bound": "hbm",
                     "achieved": round(fft_b / (fft_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(fft_b / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": round(fft_ms, 5)}
     mode_name = {0: "mean patches", 1: "binomial fluctuation", 2: "Poisson fluctuation",
