@@ -587,12 +587,9 @@ void k_wire_fused(
     const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
     int64_t strideM, int batch) {
     extern __shared__ float2 lds[];
-    // block -> (tile, item) of a batch sharing this plane shape and response:
-    // consecutive linear indices run on one XCD, items fastest, so the
-    // blocks of one tile for every item run together and read the tile's
-    // response slabs from that XCD's L2 (one HBM read per tile and batch)
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = lin / batch, item = lin - tile * batch;
+    // block -> (tile, item) of a batch sharing this plane shape and response
+    int tile, item;
+    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, batch, C, tile, item);
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
     const int Wf = plan.n, tid = threadIdx.x, T = NT;
@@ -817,8 +814,8 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
     extern __shared__ float2 lds[];
     using Fft = StaticFft<N, C, NT, R0, Rm...>;
     constexpr int NB = Fft::NB;
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = lin / batch, item = lin - tile * batch;
+    int tile, item;
+    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, batch, C, tile, item);
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
     Fft fx(lds, plan, threadIdx.x);
@@ -1178,8 +1175,8 @@ void k_wire_adjoint_items_static(const float2* __restrict__ Gt, int64_t ldG, int
     using Fft = StaticFft<N, C, NT, R0, Rm...>;
     constexpr int NB = Fft::NB;
     Fft fx(lds, plan, threadIdx.x);
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = lin / groups, grp = lin - tile * groups;
+    int tile, grp;
+    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, groups, C, tile, grp);
     const int per = (batch + groups - 1) / groups;
     const int b0 = grp * per, b1 = min(batch, b0 + per);
     if (groups > 1 && dR) {
@@ -1323,8 +1320,8 @@ __global__ __launch_bounds__(NT) void k_wire_adjoint_items(
     float2* tw = lds + Wf * C;
     fill_full_table(tw, Wf, tid, T);
     const TwFull twf{tw};
-    const int lin = xcd_tile(blockIdx.x, gridDim.x);
-    const int tile = lin / groups, grp = lin - tile * groups;
+    int tile, grp;
+    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, groups, C, tile, grp);
     const int per = (batch + groups - 1) / groups;
     const int b0 = grp * per, b1 = min(batch, b0 + per);
     if (groups > 1 && dR) {

@@ -399,6 +399,31 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * per + min(x, rem) + idx;
 }
 
+// (tile, item) of the linear block index lin over ntiles column tiles of C
+// complex columns by nitem items (a batch's items, or item groups).  The
+// tiles whose row segments share one 128-byte line (16 / C of them) come
+// next to each other for one item, then the same tiles for the next item,
+// then the next group of tiles: consecutive indices run together on one XCD
+// (xcd_tile), so each line of an item's rows is fetched once for all the
+// tiles that use it, and a tile group's response slabs are read from that
+// XCD's L2 by every item.  (With the items of one tile next to each other
+// instead, a line came back from HBM once per tile that used it: with
+// 4-column tiles the batched pass fetched its grid spectra four times.)
+__device__ __forceinline__ void tile_item(int lin, int ntiles, int nitem, int C, int& tile, int& item) {
+    const int gt = C >= 16 ? 1 : 16 / C;
+    const int full = ntiles / gt;
+    const int lfull = full * gt * nitem;
+    if (lin < lfull) {
+        const int grp = lin / (gt * nitem), rem = lin - grp * gt * nitem;
+        item = rem / gt;
+        tile = grp * gt + (rem - item * gt);
+    } else {   // the last, partial group of tiles
+        const int r = ntiles - full * gt, rem = lin - lfull;
+        item = rem / r;
+        tile = full * gt + (rem - item * r);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 int device_cus();   // compute units of the current device (cached)
 
