@@ -17,6 +17,7 @@
 // All three are bound by HBM traffic: every transform lives in LDS and each
 // grid element is read and written once per pass.
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <utility>
 
@@ -189,8 +190,9 @@ __device__ __forceinline__ void r2c_split(const float2* A, const float2* h, int 
 // persistent workgroup loops over rows and loads the next row while the
 // current one is transformed.  When every thread holds exactly the inputs
 // of one first-pass butterfly (VPT = first radix, NT * VPT = Tf/2) that
-// pass runs in registers straight from the loads.
-template <int VPT, int NT, int PM, int REG>
+// pass runs in registers straight from the loads.  SF (optional): the
+// remaining passes with the plan fixed at compile time (InplaceRowFft).
+template <int VPT, int NT, int PM, int REG, class SF = void>
 __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
                                                           int64_t ld_in, int n_in, int nrows,
                                                           FftPlan plan, float2* __restrict__ out,
@@ -234,7 +236,8 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(const float* __restrict__ in,
 #pragma unroll
             for (int r = 0; r < VPT; ++r) A[lidx<1>(tid * VPT + r)] = u[r];
             lds_barrier();
-            row_fft<VPT, PM>(A, plan, tid, T, h, tp, false, 1);
+            if constexpr (std::is_void<SF>::value) row_fft<VPT, PM>(A, plan, tid, T, h, tp, false, 1);
+            else SF::run(A, tp, tid, false);   // the passes after the first, compile-time plan
             r2c_split(A, h, Nh, tid, T, out + (int64_t)row * ld_out);
         }
         return;
@@ -270,7 +273,7 @@ __device__ __forceinline__ void load_spec_pairs(const float2* __restrict__ X, in
     }
 }
 
-template <int VPT, int NT, int PM>
+template <int VPT, int NT, int PM, class SF = void>
 __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
                                                           int64_t ld_in, int nrows, FftPlan plan,
                                                           float* __restrict__ out, int64_t ld_out,
@@ -313,7 +316,8 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(const float2* __restrict__ in,
         if (row + (int)gridDim.x < nrows)
             load_spec_pairs<VH>(in + (int64_t)(row + gridDim.x) * ld_in, Nh, tid, T, xa, xb);
         lds_barrier();
-        row_fft<VPT, PM>(A, plan, tid, T, h, tp, true, 0);
+        if constexpr (std::is_void<SF>::value) row_fft<VPT, PM>(A, plan, tid, T, h, tp, true, 0);
+        else SF::run(A, tp, tid, true);   // compile-time plan
         float* y = out + (row_off ? row_off[row] : (int64_t)row * ld_out);
         if (pairs_ok) {
             float2* y2 = reinterpret_cast<float2*>(y);
@@ -446,6 +450,12 @@ bool row_sched_ok(int nt_fft, int threads, int order) {
 // Row kernels: one row per workgroup at a time, a persistent grid of
 // 4 workgroups per CU.  threads = 0 selects the default: 256 threads for
 // half-lengths up to 1024, 512 up to 4096 and 1024 above.
+// Tf/2 = 3072 with the plan 8 8 8 6 (radix order 4) has compile-time row kernels.
+static bool plan_is_8886(const FftPlan& plan) {
+    return plan.n == 3072 && plan.npass == 4 && plan.radix[0] == 8 && plan.radix[1] == 8 && plan.radix[2] == 8 &&
+           plan.radix[3] == 6;
+}
+
 hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, int nt_fft,
                            float2* out, int64_t ld_out, hipStream_t s, int threads, int order,
                            const int64_t* row_in, bool row_in_even) {
@@ -463,6 +473,14 @@ hipError_t launch_r2c_rows(const float* in, int64_t ld_in, int n_in, int nrows, 
                              : 0;
     // the first pass runs in registers when each thread holds one butterfly
     const bool reg = pm && pairs_ok && plan.radix[0] == vpt && threads * vpt == Nh && vpt >= 2;
+    if (reg && threads == 384 && plan_is_8886(plan)) {   // Tf = 6144 with the default plan
+        using SF = InplaceRowFft<3072, 384, 8, 7, 8, 8, 6>;
+        auto kern = k_r2c_rows<8, 384, 1, 1, SF>;
+        set_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(row_grid(kern, 384, lds, nrows)), dim3(384), lds, s, in, ld_in, n_in, nrows,
+                           plan, out, ld_out, pairs_ok, row_in);
+        return hipGetLastError();
+    }
 #define LAR_R2C_PM(V, T, PM, RG)                                                                      \
     {                                                                                                 \
         set_lds(k_r2c_rows<V, T, PM, RG>, lds);                                                       \
@@ -495,6 +513,14 @@ hipError_t launch_c2r_rows(const float2* in, int64_t ld_in, int nrows, int nt_ff
                           (row_off == nullptr || row_off_even))
                              ? 1
                              : 0;
+    if (pm && threads == 384 && plan_is_8886(plan)) {   // Tf = 6144 with the default plan
+        using SF = InplaceRowFft<3072, 384, 1, 0, 8, 8, 8, 6>;
+        auto kern = k_c2r_rows<8, 384, 1, SF>;
+        set_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(row_grid(kern, 384, lds, nrows)), dim3(384), lds, s, in, ld_in, nrows, plan,
+                           out, ld_out, n_out, scale, pairs_ok, row_off);
+        return hipGetLastError();
+    }
 #define LAR_C2R_PM(V, T, PM)                                                                    \
     {                                                                                           \
         set_lds(k_c2r_rows<V, T, PM>, lds);                                                     \
@@ -684,26 +710,6 @@ void k_wire_fused(
 // response slab: one barrier per pass but the last, and every LDS index is
 // a thread constant plus a compile-time offset.  The sum over offsets goes
 // through the same passes inverted.
-template <int... Rs>
-struct RadixList {};
-template <int... Rs>
-struct RadixProd {
-    static constexpr int v = 1;
-};
-template <int R, int... Rs>
-struct RadixProd<R, Rs...> {
-    static constexpr int v = R * RadixProd<Rs...>::v;
-};
-// entries of the pass-major table taken by passes of radices Rs from Ns = NS on
-template <int NS, int... Rs>
-struct TableSpan {
-    static constexpr int v = 0;
-};
-template <int NS, int R, int... Rs>
-struct TableSpan<NS, R, Rs...> {
-    static constexpr int v = NS * (R - 1) + TableSpan<NS * R, Rs...>::v;
-};
-
 // One middle Stockham pass (radix R, sub-transform size NS) of C interleaved
 // N-point transforms from src to dst (both padded).
 template <int N, int C, int NT, int NS, int R>

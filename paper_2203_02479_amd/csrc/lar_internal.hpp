@@ -391,6 +391,83 @@ __device__ __forceinline__ void fft_lds_pm(float2* A, const FftPlan& plan, int t
     }
 }
 
+template <int... Rs>
+struct RadixList {};
+template <int... Rs>
+struct RadixProd {
+    static constexpr int v = 1;
+};
+template <int R, int... Rs>
+struct RadixProd<R, Rs...> {
+    static constexpr int v = R * RadixProd<Rs...>::v;
+};
+// entries of the pass-major table taken by passes of radices Rs from Ns = NS on
+template <int NS, int... Rs>
+struct TableSpan {
+    static constexpr int v = 0;
+};
+template <int NS, int R, int... Rs>
+struct TableSpan<NS, R, Rs...> {
+    static constexpr int v = NS * (R - 1) + TableSpan<NS * R, Rs...>::v;
+};
+
+// One in-place Stockham pass (radix R, sub-transform size NS) of a single
+// N-point sequence in the padded A by NT threads, all indices and strides
+// compile-time: every butterfly's inputs are read, a barrier, its outputs
+// written, a barrier.
+template <int N, int NT, int NS, int R>
+__device__ __forceinline__ void inplace_pass(float2* A, const float2* __restrict__ tw, int tid, bool inv) {
+    constexpr int NB = N / R, MAXB = (NB + NT - 1) / NT;
+    float2 x[MAXB][R];
+    int ob[MAXB];
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        const int b = tid + m * NT;
+        ob[m] = -1;
+        if (NB % NT == 0 || b < NB) {
+            const int k = b % NS, li = lidx<1>(b);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                // (when NB is a multiple of 32 the pad advances by exactly NB / 32)
+                float2 y = A[NB % 32 == 0 ? li + r * (NB + NB / 32) : lidx<1>(b + r * NB)];
+                if (r > 0) y = inv ? cmulc(y, tw[k * (R - 1) + r - 1]) : cmul(y, tw[k * (R - 1) + r - 1]);
+                x[m][r] = y;
+            }
+            ob[m] = (b - k) * R + k;
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int m = 0; m < MAXB; ++m) {
+        if (NB % NT == 0 || ob[m] >= 0) {
+            dft_small<R>(x[m], inv);
+            const int lo = lidx<1>(ob[m]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) A[NS % 32 == 0 ? lo + r * (NS + NS / 32) : lidx<1>(ob[m] + r * NS)] = x[m][r];
+        }
+    }
+    lds_barrier();
+}
+
+// The passes Rs... of an N-point transform in A from sub-transform size NS
+// on (the passes before were done elsewhere), twiddles at tp + TOFF.
+template <int N, int NT, int NS, int TOFF>
+__device__ __forceinline__ void inplace_passes(RadixList<>, float2*, const float2*, int, bool) {}
+template <int N, int NT, int NS, int TOFF, int R, int... Rest>
+__device__ __forceinline__ void inplace_passes(RadixList<R, Rest...>, float2* A, const float2* tp, int tid, bool inv) {
+    inplace_pass<N, NT, NS, R>(A, tp + TOFF, tid, inv);
+    inplace_passes<N, NT, NS * R, TOFF + NS * (R - 1)>(RadixList<Rest...>{}, A, tp, tid, inv);
+}
+
+// A row transform with its plan fixed at compile time, for the row kernels:
+// the passes Rs... from sub-transform size NS0 (and table entry TOFF0) on.
+template <int N, int NT, int NS0, int TOFF0, int... Rs>
+struct InplaceRowFft {
+    __device__ static void run(float2* A, const float2* tp, int tid, bool inv) {
+        inplace_passes<N, NT, NS0, TOFF0>(RadixList<Rs...>{}, A, tp, tid, inv);
+    }
+};
+
 // blockIdx -> tile with consecutive tiles on one XCD (workgroups are dealt
 // round-robin over the 8 XCDs, each with its own L2).
 __device__ __forceinline__ int xcd_tile(int b, int G) {
