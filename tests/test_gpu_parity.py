@@ -134,6 +134,28 @@ def test_fftconv_random_grid_and_spectrum(case):
     ref = oracle.conv_fft(P, g, R)
     assert np.isfinite(w).all()
     assert rel_l2(w, ref) < RTOL_L2
+    assert np.max(np.abs(w - ref)) <= RTOL_L2 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("case", [dict(n_wires=21, n_ticks=6144, n_imp=4, nt_fft=6144, nw_fft=512),
+                                  dict(n_wires=30, n_ticks=1024, n_imp=3, nt_fft=1024, nw_fft=864)])
+@pytest.mark.parametrize("column", ["dc", "nyquist"])
+def test_fftconv_dc_and_nyquist_columns(case, column):
+    """Grids whose every row is constant (all of its spectrum in the DC
+    column) or alternates in sign tick by tick (all in the Nyquist column,
+    n_ticks = Tf): an error in the wire pass's first or last column tile
+    (the Nyquist column is a tile of its own at Wf 512 with 16-column tiles)
+    then dominates the waveforms instead of hiding among 3073 columns."""
+    P = inputs.Plane(**case)
+    rng = np.random.default_rng(17)
+    amp = rng.standard_normal((P.n_rows, 1)).astype(np.float32)
+    sign = np.ones(P.n_ticks, np.float32) if column == "dc" else (-1.0) ** np.arange(P.n_ticks, dtype=np.float32)
+    g = (amp * sign[None, :]).astype(np.float32)
+    R = inputs.random_spectrum(P, 18)
+    w = gpu_fftconv(P, g, R)
+    ref = oracle.conv_fft(P, g, R)
+    assert rel_l2(w, ref) < RTOL_L2
+    assert np.max(np.abs(w - ref)) <= RTOL_L2 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("case", [dict(n_wires=64, n_ticks=1024, nt_fft=1024, nw_fft=96, kind="unipolar"),
@@ -148,6 +170,7 @@ def test_response_spectrum(case):
     ref = oracle.response_spectrum(P, r)
     got = resp[..., 0] + 1j * resp[..., 1]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < RTOL_L2
+    assert np.max(np.abs(got - ref)) <= RTOL_L2 * np.max(np.abs(ref))
 
 
 def test_fftconv_equals_direct_sum_tiny():
@@ -158,7 +181,9 @@ def test_fftconv_equals_direct_sum_tiny():
     S = rng.standard_normal((P.n_rows, P.n_ticks)).astype(np.float32)
     resp = _lar().spectrum_from_time(P, r).cpu().numpy()
     w = gpu_fftconv(P, S, resp)
-    assert rel_l2(w, oracle.conv_direct(P, r, S)) < RTOL_L2
+    ref = oracle.conv_direct(P, r, S)
+    assert rel_l2(w, ref) < RTOL_L2
+    assert np.max(np.abs(w - ref)) <= RTOL_L2 * np.max(np.abs(ref))
 
 
 # ------------------------------------------------------------------ end to end
@@ -182,6 +207,7 @@ def test_sim_plane_mean(cfg):
     w = _sim_plane(P, dep, resp_dev)
     ref = oracle.sim_plane_mean(P, dep, oracle.response_spectrum(P, r))
     assert rel_l2(w, ref) < RTOL_L2
+    assert np.max(np.abs(w - ref)) <= RTOL_L2 * np.max(np.abs(ref))
 
 
 # ------------------------------------------------------------------ fluctuation

@@ -53,6 +53,7 @@ def test_every_candidate_schedule_matches_oracle(case):
             w = wave.cpu().numpy()
             assert np.isfinite(w).all(), c
             assert rel_l2(w, ref) < RTOL_L2, c
+            assert np.max(np.abs(w - ref)) <= RTOL_L2 * np.max(np.abs(ref)), c
     finally:
         lar.schedule_set(P, None)
 
