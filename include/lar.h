@@ -77,6 +77,13 @@ typedef struct lar_depos {
     int64_t n;
 } lar_depos;
 
+/* The optional counter of skipped depos: *count (device, one int64, 8-byte
+ * aligned, written on `stream`, not accumulated) = the number of depos with
+ * a non-finite field, the ones every raster call skips.  Stream-ordered and
+ * allocation-free (no memset node: a graph may capture it).  LAR_EINVAL for
+ * a null depos or count or a depos that lar_raster would reject. */
+int lar_depos_nonfinite(const lar_depos *depos, int64_t *count, void *stream);
+
 /* Charge fluctuation (paper Sec. 3.1: the reference code draws binomial
  * electron counts, the GPU port a normal approximation).  mode 0: mean
  * patch q*wt*wx; 1: Binomial(rint|q|, p) per bin; 2: Poisson(|q| p) per

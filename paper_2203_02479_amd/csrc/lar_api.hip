@@ -156,6 +156,15 @@ static int raster_impl(const lar_plane* plane, const lar_depos* depos, float nsi
     return LAR_OK;
 }
 
+int lar_depos_nonfinite(const lar_depos* depos, int64_t* count, void* stream) {
+    int st;
+    if ((st = check_depos(depos))) return st;
+    if (!count) return LAR_EINVAL;
+    LAR_TRY(launch_count_nonfinite(depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x, depos->n, count,
+                                   (hipStream_t)stream));
+    return LAR_OK;
+}
+
 int lar_raster(const lar_plane* plane, const lar_depos* depos, float nsigma, const lar_fluct* fluct,
                float* grid, void* ws, size_t ws_bytes, void* stream) {
     int st;

@@ -582,6 +582,9 @@ hipError_t launch_raster(const RasterArgs& a, const float* q, const float* t, co
 hipError_t launch_raster_items(int mode, const RasterItem& one, const RasterItem* items, int n_items,
                                int64_t total_sub, void* ws, size_t ws_bytes, hipStream_t s,
                                hipEvent_t main_done = nullptr, int tile = kRasterTileDefault);
+// *count (device) = the number of depos with a non-finite field.
+hipError_t launch_count_nonfinite(const float* q, const float* t, const float* x, const float* st,
+                                  const float* sx, int64_t n, int64_t* count, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, const float* q, const float* t, const float* x,
                              const float* st, const float* sx, int64_t n, const float* grid_grad,
                              float* dq, float* dt, float* dx, float* dst, float* dsx, hipStream_t s);

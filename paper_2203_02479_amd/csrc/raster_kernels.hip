@@ -1576,6 +1576,47 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_wide(RasterItem one,
     }
 }
 
+// ---------------------------------------------------------------- skipped depos
+//
+// The depos every raster kernel skips (a non-finite field, depo_finite),
+// counted into a device 64-bit counter: the counter is cleared by one
+// thread of a one-block kernel, then each workgroup sums its wave counts in
+// LDS and adds the total with one atomic (integer sums: the count does not
+// depend on the order).
+__global__ __launch_bounds__(64) void k_clear_count(unsigned long long* count) {
+    if (threadIdx.x == 0) *count = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_count_nonfinite(const float* __restrict__ q, const float* __restrict__ t,
+                                                         const float* __restrict__ x, const float* __restrict__ st,
+                                                         const float* __restrict__ sx, int64_t n,
+                                                         unsigned long long* __restrict__ count) {
+    __shared__ unsigned s_part[4];
+    unsigned c = 0;
+    const int64_t step = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += step)
+        c += depo_finite(q[i], t[i], x[i], st[i], sx[i]) ? 0u : 1u;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned total = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        if (total) atomicAdd(count, (unsigned long long)total);
+    }
+}
+
+hipError_t launch_count_nonfinite(const float* q, const float* t, const float* x, const float* st,
+                                  const float* sx, int64_t n, int64_t* count, hipStream_t s) {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(count);
+    hipLaunchKernelGGL(k_clear_count, dim3(1), dim3(64), 0, s, c);
+    if (n > 0) {
+        const int64_t blocks = (n + 255) / 256, cap = 8 * (int64_t)device_cus();
+        hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, s, q, t,
+                           x, st, sx, n, c);
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- adjoint raster
 //
 // Gradients of L = sum_{m,j} G[m][j] S[m][j] with respect to each depo's q,

@@ -109,6 +109,7 @@ SIGNATURES = {
                         ctypes.c_int),
     "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
+    "lar_depos_nonfinite": ([_P(lar_depos), _VP, _VP], ctypes.c_int),
     "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_get": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_set": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
@@ -214,6 +215,17 @@ def workspace(nbytes, device="cuda"):
 
 
 # ---------------------------------------------------------------- calls
+
+def depos_nonfinite(depos: DeviceDepos, out=None, stream=None):
+    """Number of depositions with a non-finite field (the ones the raster
+    skips), counted on the GPU into out (a one-element int64 device tensor,
+    allocated when None).  Returns out; out.item() synchronises."""
+    if out is None:
+        out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ds = depos.struct()
+    _check(_lib().lar_depos_nonfinite(ctypes.byref(ds), _ptr(out), _stream(stream)), "lar_depos_nonfinite")
+    return out
+
 
 def raster_workspace(plane, n_depos, fluct) -> int:
     n = ctypes.c_size_t(0)

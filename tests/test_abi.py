@@ -157,6 +157,18 @@ def test_stage_calls_host_side_errors(lar):
     assert L.lar_noise(ctypes.byref(pl), one, 0, 0, 1, one, one, 256, None) == lar.LAR_EWORKSPACE
 
 
+def test_nonfinite_counter_host_side_errors(lar):
+    L = lar.lib()
+    one = ctypes.c_void_p(16)
+    good = lar.lar_depos(one, one, one, one, one, 5)
+    assert L.lar_depos_nonfinite(None, one, None) == lar.LAR_EINVAL
+    assert L.lar_depos_nonfinite(ctypes.byref(good), None, None) == lar.LAR_EINVAL
+    for bad in (lar.lar_depos(one, None, one, one, one, 5), lar.lar_depos(one, one, one, one, one, -1)):
+        assert L.lar_depos_nonfinite(ctypes.byref(bad), one, None) == lar.LAR_EINVAL
+    huge = lar.lar_depos(one, one, one, one, one, 1 << 33)
+    assert L.lar_depos_nonfinite(ctypes.byref(huge), one, None) == lar.LAR_ESIZE
+
+
 def test_schedule_registry_host_side(lar):
     P = inputs.cfg1_plane()
     d = lar.schedule_default(P)

@@ -99,6 +99,26 @@ def test_raster_degenerate_depos():
     assert not gpu_raster(P, empty).any()
 
 
+def test_nonfinite_depos_counter():
+    """lar_depos_nonfinite counts the depos the raster skips: any NaN or
+    infinite field, in any of the five arrays; 0 for an empty set."""
+    torch, lar = _torch(), _lar()
+    rng = np.random.default_rng(23)
+    n = 300_001
+    arrs = [rng.standard_normal(n).astype(np.float32) for _ in range(5)]
+    for k, a in enumerate(arrs):
+        idx = rng.choice(n, 700 + 100 * k, replace=False)
+        a[idx] = rng.choice(np.array([np.nan, np.inf, -np.inf], np.float32), idx.size)
+    dep = inputs.Depos(*arrs)
+    expect = int(np.sum(~np.all(np.isfinite(np.stack(arrs)), axis=0)))
+    out = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+    assert lar.depos_nonfinite(lar.DeviceDepos.from_host(dep), out).item() == expect
+    # the count is written, not accumulated
+    assert lar.depos_nonfinite(lar.DeviceDepos.from_host(dep), out).item() == expect
+    empty = inputs.Depos(*(np.zeros(0, np.float32) for _ in range(5)))
+    assert lar.depos_nonfinite(lar.DeviceDepos.from_host(empty), out).item() == 0
+
+
 def test_raster_accumulates():
     torch, lar = _torch(), _lar()
     ev = inputs.cfg0_event()
