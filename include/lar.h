@@ -81,7 +81,8 @@ typedef struct lar_depos {
  * aligned, written on `stream`, not accumulated) = the number of depos with
  * a non-finite field, the ones every raster call skips.  Stream-ordered and
  * allocation-free (no memset node: a graph may capture it).  LAR_EINVAL for
- * a null depos or count or a depos that lar_raster would reject. */
+ * a null depos, a null or misaligned count, or a depos that lar_raster would
+ * reject (LAR_ESIZE above 2^32 depos). */
 int lar_depos_nonfinite(const lar_depos *depos, int64_t *count, void *stream);
 
 /* Charge fluctuation (paper Sec. 3.1: the reference code draws binomial

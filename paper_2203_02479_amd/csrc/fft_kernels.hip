@@ -769,7 +769,8 @@ struct StaticFft {
     float2* buf1;
     float2* tp;
     int tid, j, s, e0, i1, li1, par;
-    // builds the twiddle table (callers synchronise before the first run)
+    // builds the twiddle table; the first barrier of run, before any pass
+    // reads it, orders the build
     __device__ StaticFft(float2* lds, const FftPlan& plan, int tid_)
         : buf0(lds), buf1(lds + SL), tp(lds + 2 * SL), tid(tid_), j(tid_ / C), s(tid_ % C), par(0) {
         e0 = j * R0 * C + s;

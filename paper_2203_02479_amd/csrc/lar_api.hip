@@ -159,7 +159,7 @@ static int raster_impl(const lar_plane* plane, const lar_depos* depos, float nsi
 int lar_depos_nonfinite(const lar_depos* depos, int64_t* count, void* stream) {
     int st;
     if ((st = check_depos(depos))) return st;
-    if (!count) return LAR_EINVAL;
+    if (!count || reinterpret_cast<uintptr_t>(count) % 8) return LAR_EINVAL;   // a 64-bit atomic target
     LAR_TRY(launch_count_nonfinite(depos->q, depos->t, depos->x, depos->sigma_t, depos->sigma_x, depos->n, count,
                                    (hipStream_t)stream));
     return LAR_OK;

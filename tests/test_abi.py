@@ -163,6 +163,7 @@ def test_nonfinite_counter_host_side_errors(lar):
     good = lar.lar_depos(one, one, one, one, one, 5)
     assert L.lar_depos_nonfinite(None, one, None) == lar.LAR_EINVAL
     assert L.lar_depos_nonfinite(ctypes.byref(good), None, None) == lar.LAR_EINVAL
+    assert L.lar_depos_nonfinite(ctypes.byref(good), ctypes.c_void_p(20), None) == lar.LAR_EINVAL
     for bad in (lar.lar_depos(one, None, one, one, one, 5), lar.lar_depos(one, one, one, one, one, -1)):
         assert L.lar_depos_nonfinite(ctypes.byref(bad), one, None) == lar.LAR_EINVAL
     huge = lar.lar_depos(one, one, one, one, one, 1 << 33)
