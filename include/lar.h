@@ -402,17 +402,20 @@ int lar_sim_streams(const lar_plane *planes, int32_t n_types, const float *const
  * computes the same transform up to float rounding; which one is fastest
  * depends on the shape.  Schedules are keyed by (n_wires, n_imp, n_ticks,
  * nt_fft, nw_fft), process-wide, and read when a call launches its kernels
- * (lar_batch_create reads them once).  Radix orders 0..4 pick the order of
+ * (lar_batch_create reads them once).  Radix orders 0..5 pick the order of
  * the radix-8/6/4/3/2 passes of a transform:
  *   0: 8s (then one 4 or 2), then 3s   1: 4s, 3s, then one 2
  *   2: 3s, then 8s (then one 4 or 2)  3: the reverse of 0
- *   4: 8s, then each remaining 2 paired with a 3 as a 6, then the rest */
+ *   4: 8s, then each remaining 2 paired with a 3 as a 6, then the rest
+ *   5: radix 6 first and last (needs 36 | n); between them 8s, a 4 or 2,
+ *      6s, then 3s (864: 6 4 6 6) */
 typedef struct lar_schedule {
     int32_t row_threads;    /* threads per time-axis row workgroup: 256, 384, 512, 768, 1024 */
     int32_t row_order;      /* radix order of the nt_fft/2-point plan */
     int32_t wire_cols;      /* time-frequency columns per wire-pass tile: 4, 8, 16 */
     int32_t wire_threads;   /* threads per wire-pass workgroup: 256, 512, 1024
-                               (cols 4: 256/512; cols 16: 512/1024) */
+                               (cols 4: 256/512; cols 16: 512/1024), or 576 with
+                               cols 4 and the nw_fft = 864 plan 6 4 6 6 (order 5) */
     int32_t wire_order;     /* radix order of the nw_fft-point plan */
     int32_t raster_tile;    /* floats of a raster wave's LDS tile: 384, 512, 640, 768
                                (0 in lar_schedule_set: the built-in 512).  A wave sums

@@ -8,9 +8,9 @@
 //               the response spectrum of offset k and accumulate; then one
 //               inverse FFT over wires.  The impact-offset reduction never
 //               leaves the chip.
-//  k_wire_static the same with the plan fixed at compile time (Wf = 512,
-//               8 8 8): first and last pass in registers, two barriers per
-//               offset; k_wire_adjoint_static and k_wire_adjoint_items_static
+//  k_wire_static the same with the plan fixed at compile time (Wf = 512:
+//               8 8 8; Wf = 864: 6 4 6 6): first and last pass in
+//               registers, one barrier per pass but the last; k_wire_adjoint_static and k_wire_adjoint_items_static
 //               likewise for the adjoint.
 //  k_c2r_rows   inverse real FFT along ticks, scaled by 1/(Wf Tf), cropped.
 //
@@ -49,6 +49,20 @@ bool make_plan(int n, FftPlan* plan, int order) {
         if (x == 2) r[np++] = 4;
         if (x == 1) r[np++] = 2;
         for (int i = 0; i < y; ++i) r[np++] = 3;
+    } else if (order == 5) {
+        // radix 6 first and last; between them 8s, then a 4 or 2, then the
+        // remaining 2 x 3 pairs as 6s, then 3s (864: 6 4 6 6)
+        if (a < 2 || b < 2) return false;
+        int x = a - 2, y = b - 2;
+        r[np++] = 6;
+        while (x >= 3 && x - 3 >= y) { r[np++] = 8; x -= 3; }
+        while (x > y) {
+            if (x - y >= 2) { r[np++] = 4; x -= 2; }
+            else { r[np++] = 2; --x; }
+        }
+        while (x > 0 && y > 0) { r[np++] = 6; --x; --y; }
+        for (int i = 0; i < y; ++i) r[np++] = 3;
+        r[np++] = 6;
     } else if (order == 1) {
         int x = a;
         while (x >= 2) { r[np++] = 4; x -= 2; }
@@ -812,9 +826,12 @@ struct StaticFft {
 // the last pass back into registers, where its outputs meet the response
 // slab: one barrier per pass but the last, and every LDS index is a thread
 // constant plus a compile-time offset.  The sum over offsets goes through
-// the same passes inverted.
-template <int N, int C, int NT, int R0, int... Rm>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// the same passes inverted.  PREF: the next offset's response slab is
+// requested right after this offset's product (else right after this
+// offset's transform, which spares its registers: with 576 threads, two
+// workgroups per CU need at most 96 per lane).
+template <int N, int C, int NT, bool PREF, int R0, int... Rm>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 576 ? 5 : 4, 8)))
 void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n_imp, int F, FftPlan plan,
                    const float2* __restrict__ R, float2* __restrict__ M, int64_t ldM, int64_t strideS,
                    int64_t strideM, int batch) {
@@ -854,7 +871,7 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
         }
     };
     gather_s(0);
-    gather_r(0);
+    if (PREF) gather_r(0);
     for (int k = 0; k < n_imp; ++k) {
         float2 x[R0];
 #pragma unroll
@@ -864,12 +881,13 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
         }
         if (k + 1 < n_imp) gather_s(k + 1);
         fx.run(x, false);
+        if (!PREF) gather_r(k);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             acc[r].x += x[r].x * rr[r].x - x[r].y * rr[r].y;
             acc[r].y += x[r].x * rr[r].y + x[r].y * rr[r].x;
         }
-        if (k + 1 < n_imp) gather_r(k + 1);
+        if (PREF && k + 1 < n_imp) gather_r(k + 1);
     }
     fx.run(acc, true);
 #pragma unroll
@@ -893,7 +911,27 @@ static hipError_t wire_launch_888(const float2* S, int64_t ldS, int n_wires, int
                                   int64_t strideS, int64_t strideM, hipStream_t s) {
     const size_t lds = static_lds_bytes(plan, C);
     dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(64 * C);
-    auto kern = k_wire_static<512, C, 64 * C, 8, 8>;
+    auto kern = k_wire_static<512, C, 64 * C, true, 8, 8>;
+    set_lds(kern, lds);
+    hipLaunchKernelGGL(kern, grid, block, lds, s, S, ldS, n_wires, n_imp, F, plan, R, M, ldM, strideS, strideM,
+                       batch);
+    return hipGetLastError();
+}
+
+// Wf = 864 with the plan 6 4 6 6 (radix order 5), 4 columns x 576 threads,
+// takes k_wire_static without the response prefetch.
+static bool plan_is_6466(const FftPlan& plan) {
+    return plan.n == 864 && plan.npass == 4 && plan.radix[0] == 6 && plan.radix[1] == 4 && plan.radix[2] == 6 &&
+           plan.radix[3] == 6;
+}
+
+static hipError_t wire_launch_6466(const float2* S, int64_t ldS, int n_wires, int n_imp, int F,
+                                   const FftPlan& plan, const float2* R, float2* M, int64_t ldM, int batch,
+                                   int64_t strideS, int64_t strideM, hipStream_t s) {
+    constexpr int C = 4, NT = 576;
+    const size_t lds = static_lds_bytes(plan, C);
+    dim3 grid((unsigned)(((F + C - 1) / C) * batch)), block(NT);
+    auto kern = k_wire_static<864, C, NT, false, 6, 4, 6>;
     set_lds(kern, lds);
     hipLaunchKernelGGL(kern, grid, block, lds, s, S, ldS, n_wires, n_imp, F, plan, R, M, ldM, strideS, strideM,
                        batch);
@@ -922,13 +960,17 @@ static hipError_t wire_launch(const float2* S, int64_t ldS, int n_wires, int n_i
 }
 
 // Default wire tiles: 16 columns x 1024 threads for Wf = 512 (k_wire_static,
-// whole 128-byte row segments), 8 x 512 below, 4 x 512 above (more resident
-// workgroups per CU).
+// whole 128-byte row segments), 4 x 576 with radix order 5 for Wf = 864
+// (k_wire_static, 6 4 6 6), 8 x 512 below 512, 4 x 512 otherwise (more
+// resident workgroups per CU).
 int default_wire_cols(int nw_fft) { return nw_fft == 512 ? 16 : (nw_fft < 512 ? 8 : 4); }
-int default_wire_threads(int nw_fft) { return nw_fft == 512 ? 1024 : 512; }
+int default_wire_threads(int nw_fft) { return nw_fft == 512 ? 1024 : (nw_fft == 864 ? 576 : 512); }
+int default_wire_order(int nw_fft) { return nw_fft == 864 ? 5 : 0; }
 
 bool wire_sched_ok(int nw_fft, int cols, int threads, int order) {
     FftPlan plan;
+    if (cols == 4 && threads == 576)   // k_wire_static with the 6 4 6 6 plan only
+        return make_plan(nw_fft, &plan, order) && plan_is_6466(plan) && static_lds_bytes(plan, 4) <= kLdsBytes;
     const bool shape = (cols == 4 && (threads == 256 || threads == 512)) ||
                        (cols == 8 && (threads == 256 || threads == 512 || threads == 1024)) ||
                        (cols == 16 && (threads == 512 || threads == 1024));
@@ -946,12 +988,18 @@ hipError_t launch_wire_fused(const float2* S, int64_t ldS, int n_wires, int n_im
                              int F, const float2* R, float2* M, int64_t ldM, hipStream_t s,
                              int batch, int64_t strideS, int64_t strideM, int cols, int threads,
                              int order) {
-    if (!cols) cols = default_wire_cols(nw_fft);
+    if (!cols) {
+        cols = default_wire_cols(nw_fft);
+        threads = default_wire_threads(nw_fft);
+        order = default_wire_order(nw_fft);
+    }
     if (!threads) threads = default_wire_threads(nw_fft);
     FftPlan plan;
     if (!wire_sched_ok(nw_fft, cols, threads, order) || !make_plan(nw_fft, &plan, order))
         return hipErrorInvalidValue;
     if (F <= 0 || batch <= 0) return hipSuccess;
+    if (plan_is_6466(plan) && cols == 4 && threads == 576)
+        return wire_launch_6466(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
     if (plan_is_888(plan) && threads == 64 * cols) {
         if (cols == 4) return wire_launch_888<4>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);
         if (cols == 8) return wire_launch_888<8>(S, ldS, n_wires, n_imp, F, plan, R, M, ldM, batch, strideS, strideM, s);

@@ -20,7 +20,7 @@ namespace lar {
 // passes is a schedule choice (make_plan's `order`).
 constexpr int kMaxPasses = 16;
 constexpr size_t kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
-constexpr int kPlanOrders = 5;
+constexpr int kPlanOrders = 6;
 
 struct FftPlan {
     int n;
@@ -517,6 +517,7 @@ bool raster_tile_ok(int tile);   // 384, 512, 640 or 768
 int default_row_threads(int nt_fft);
 int default_wire_cols(int nw_fft);
 int default_wire_threads(int nw_fft);
+int default_wire_order(int nw_fft);
 bool row_sched_ok(int nt_fft, int threads, int order);
 bool wire_sched_ok(int nw_fft, int cols, int threads, int order);
 // The schedule registered for this plane shape, else the default one.

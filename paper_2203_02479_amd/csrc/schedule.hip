@@ -31,7 +31,7 @@ Sched sched_default(int nt_fft, int nw_fft) {
     s.row_order = 4;   // radix 8 first, 2 x 3 merged into radix 6
     s.wire_cols = default_wire_cols(nw_fft);
     s.wire_threads = default_wire_threads(nw_fft);
-    s.wire_order = 0;
+    s.wire_order = default_wire_order(nw_fft);
     s.raster_tile = kRasterTileDefault;
     return s;
 }
@@ -136,7 +136,7 @@ int lar_schedule_candidates(const lar_plane* p, lar_schedule* out, int32_t cap, 
     if ((st = check_shape(p))) return st;
     if (!n || cap < 0 || (cap > 0 && !out)) return LAR_EINVAL;
     static const int row_threads[5] = {256, 384, 512, 768, 1024};
-    static const int threads[3] = {256, 512, 1024};
+    static const int threads[4] = {256, 512, 576, 1024};   // 576: 4 columns, Wf 864's 6 4 6 6 plan
     static const int cols[3] = {4, 8, 16};
     const Sched d = sched_default(p->nt_fft, p->nw_fft);
     int count = 0;

@@ -188,8 +188,10 @@ def test_schedule_registry_host_side(lar):
         lar.schedule_set(P, None)
     assert lar.schedule_get(P) == d
     # Tf/2 = 3072 over 256 threads is 12 values per thread; 4 x 1024 is not a
-    # wire shape; radix order 5 does not exist; 16 x 512 is 16 values of Wf 512
+    # wire shape; radix order 5 needs 36 | n (3072 is not), order 6 does not
+    # exist; 16 x 512 is 16 values of Wf 512; 4 x 576 needs Wf 864's order 5
     for bad in (dict(row_threads=256), dict(wire_cols=4, wire_threads=1024), dict(row_order=5),
+                dict(row_order=6), dict(wire_cols=4, wire_threads=576),
                 dict(wire_order=-1), dict(wire_cols=16, wire_threads=512), dict(row_threads=300),
                 dict(raster_tile=500), dict(raster_tile=1024)):
         with pytest.raises(lar.LarError) as e:
@@ -223,3 +225,8 @@ def test_schedule_candidates_every_shape_valid(lar):
     assert 4 in row_orders                  # 3072 = 8 8 8 6 with a radix-6 pass
     tiles = {c["raster_tile"] for c in lar.schedule_candidates(inputs.cfg1_plane())}
     assert tiles == {384, 512, 640, 768}
+    # the 800-wire planes (Wf 864) default to the compile-time 6 4 6 6 wire pass
+    U = inputs.Plane(n_wires=800, n_ticks=6000, kind="bipolar")
+    d = lar.schedule_default(U)
+    assert (U.nw_fft, d["wire_cols"], d["wire_threads"], d["wire_order"]) == (864, 4, 576, 5)
+    assert any(c["wire_order"] == 0 and c["wire_threads"] == 512 for c in lar.schedule_candidates(U))
