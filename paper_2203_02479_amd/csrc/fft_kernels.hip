@@ -10,8 +10,9 @@
 //               leaves the chip.
 //  k_wire_static the same with the plan fixed at compile time (Wf = 512:
 //               8 8 8; Wf = 864: 6 4 6 6): first and last pass in
-//               registers, one barrier per pass but the last; k_wire_adjoint_static and k_wire_adjoint_items_static
-//               likewise for the adjoint.
+//               registers, one barrier per pass but the last;
+//               k_wire_adjoint_static and k_wire_adjoint_offsets_static
+//               (batched) likewise for the adjoint.
 //  k_c2r_rows   inverse real FFT along ticks, scaled by 1/(Wf Tf), cropped.
 //
 // All three are bound by HBM traffic: every transform lives in LDS and each
@@ -1216,32 +1217,33 @@ void k_wire_adjoint_static(const float2* __restrict__ Gt, int64_t ldG, const flo
     }
 }
 
-// k_wire_adjoint_items with a compile-time plan (StaticFft); the next item's
-// Gt rows are requested before this item's transforms, its grid-spectrum
-// rows right before the transform of Gh.
-template <int N, int C, int NT, int R0, int... Rm>
+// The batched adjoint wire pass with a compile-time plan (StaticFft): one
+// workgroup per (column tile, KG consecutive impact offsets), the items of
+// the batch as its inner loop.  Each item's Gh (the wire transform of its
+// waveform-gradient tile) is formed once per workgroup and serves the KG
+// offsets; their response gradients are summed over the items in registers
+// and written once, so no partial sums are needed; item b's grid-gradient
+// spectrum is written over its S rows (each row of offset k is read, for
+// the response gradient, before it is written, by the same thread).  PF:
+// the next item's Gt rows are requested before this item's transforms.
+template <int N, int C, int NT, int KG, bool PF, int R0, int... Rm>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_wire_adjoint_items_static(const float2* __restrict__ Gt, int64_t ldG, int64_t strideG, float2* S,
-                                 int64_t ldS, int64_t strideS, int batch, int groups, int n_wires, int n_imp,
-                                 int F, int nyq, FftPlan plan, const float2* __restrict__ R,
-                                 float2* __restrict__ dR, float2* __restrict__ part, int64_t part_stride,
-                                 float resp_scale, int accumulate) {
+void k_wire_adjoint_offsets_static(const float2* __restrict__ Gt, int64_t ldG, int64_t strideG, float2* S,
+                                   int64_t ldS, int64_t strideS, int batch, int n_wires, int n_imp, int F,
+                                   int nyq, FftPlan plan, const float2* __restrict__ R, float2* __restrict__ dR,
+                                   float resp_scale, int accumulate) {
     extern __shared__ float2 lds[];
     using Fft = StaticFft<N, C, NT, R0, Rm...>;
     constexpr int NB = Fft::NB;
     Fft fx(lds, plan, threadIdx.x);
-    int tile, grp;
-    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, groups, C, tile, grp);
-    const int per = (batch + groups - 1) / groups;
-    const int b0 = grp * per, b1 = min(batch, b0 + per);
-    if (groups > 1 && dR) {
-        dR = part + (int64_t)grp * part_stride;
-        accumulate = 0;
-    }
+    int tile, kg;
+    tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, (n_imp + KG - 1) / KG, C, tile, kg);
+    const int k0 = kg * KG, nk = min(KG, n_imp - k0);
     const int j = fx.j, s = fx.s, f0 = tile * C;
     const int f = min(f0 + s, F - 1);
     const bool f_ok = f0 + s < F;
     const float cf = (f0 + s == 0 || f0 + s == nyq) ? resp_scale : 2.f * resp_scale;
+    // unconditional gathers (clamped rows, masked at use), as in k_wire_static
     auto gather = [&](float2 (&x)[R0], const float2* base, int64_t ld, int rstride, int off) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
@@ -1254,38 +1256,40 @@ void k_wire_adjoint_items_static(const float2* __restrict__ Gt, int64_t ldG, int
 #pragma unroll
         for (int r = 0; r < R0; ++r) x[r] = (f_ok && j + NB * r < n_wires) ? x[r] : make_float2(0.f, 0.f);
     };
-    for (int k = 0; k < n_imp; ++k) {
-        float2 dacc[R0], rr[R0], g[R0];
-        const float2* Rk = R + (int64_t)k * N * F;
+    float2 dacc[KG][R0], g[R0];
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            dacc[r] = make_float2(0.f, 0.f);
-            int p = j + NB * r;
-            asm volatile("" : "+v"(p));
-            rr[r] = Rk[(int64_t)p * F + f];
-        }
-        if (b0 < b1) gather(g, Gt + (int64_t)b0 * strideG, ldG, 1, 0);
-        for (int b = b0; b < b1; ++b) {
-            float2* Sb = S + (int64_t)b * strideS;
-            float2 gh[R0], x[R0];
+    for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) gh[r] = g[r];
-            masked(gh);
-            if (dR) gather(x, Sb, ldS, n_imp, k);
-            if (b + 1 < b1) gather(g, Gt + (int64_t)(b + 1) * strideG, ldG, 1, 0);
-            fx.run(gh, false);
+        for (int r = 0; r < R0; ++r) dacc[kk][r] = make_float2(0.f, 0.f);
+    if (PF && batch > 0) gather(g, Gt, ldG, 1, 0);
+    for (int b = 0; b < batch; ++b) {
+        float2* Sb = S + (int64_t)b * strideS;
+        float2 gh[R0];
+        if (!PF) gather(g, Gt + (int64_t)b * strideG, ldG, 1, 0);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) gh[r] = g[r];
+        masked(gh);
+        if (PF && b + 1 < batch) gather(g, Gt + (int64_t)(b + 1) * strideG, ldG, 1, 0);
+        fx.run(gh, false);
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            if (kk >= nk) break;   // workgroup-uniform
+            const int k = k0 + kk;
+            float2 x[R0];
             if (dR) {
+                gather(x, Sb, ldS, n_imp, k);
                 masked(x);
                 fx.run(x, false);
 #pragma unroll
                 for (int r = 0; r < R0; ++r) {
                     const float2 q = cmulc(gh[r], x[r]);   // Gh conj(Sk)
-                    dacc[r].x += q.x;
-                    dacc[r].y += q.y;
+                    dacc[kk][r].x += q.x;
+                    dacc[kk][r].y += q.y;
                 }
             }
+            const float2* Rk = R + (int64_t)k * N * F;
 #pragma unroll
-            for (int r = 0; r < R0; ++r) x[r] = cmulc(gh[r], rr[r]);   // conj(R) Gh
+            for (int r = 0; r < R0; ++r) x[r] = cmulc(gh[r], Rk[(int64_t)(j + NB * r) * F + f]);   // conj(R) Gh
             fx.run(x, true);
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
@@ -1293,17 +1297,19 @@ void k_wire_adjoint_items_static(const float2* __restrict__ Gt, int64_t ldG, int
                 if (p < n_wires && f_ok) Sb[(int64_t)(p * n_imp + k) * ldS + f0 + s] = x[r];
             }
         }
-        if (dR) {
-            float2* dRk = dR + (int64_t)k * N * F;
+    }
+    if (dR && f_ok) {
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            if (kk >= nk) break;
+            float2* dRk = dR + (int64_t)(k0 + kk) * N * F;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                if (f_ok) {
-                    float2* o = dRk + (int64_t)(j + NB * r) * F + f0 + s;
-                    float2 cur = accumulate ? *o : make_float2(0.f, 0.f);
-                    cur.x += cf * dacc[r].x;
-                    cur.y += cf * dacc[r].y;
-                    *o = cur;
-                }
+                float2* o = dRk + (int64_t)(j + NB * r) * F + f0 + s;
+                float2 cur = accumulate ? *o : make_float2(0.f, 0.f);
+                cur.x += cf * dacc[kk][r].x;
+                cur.y += cf * dacc[kk][r].y;
+                *o = cur;
             }
         }
     }
@@ -1507,16 +1513,21 @@ hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t stri
     const int64_t pstride = (int64_t)n_imp * nw_fft * F;
     float2* part = reinterpret_cast<float2*>(scratch);
     constexpr int C = 8;
-    dim3 grid((unsigned)(((F + C - 1) / C) * groups));
-    hipError_t e = hipErrorInvalidValue;
     if (plan_is_888(plan)) {
-        auto kern = k_wire_adjoint_items_static<512, C, 64 * C, 8, 8>;
+        // one impact offset per workgroup, every item in each: no partials.
+        // (With two offsets per workgroup, sharing each Gh, the two response
+        // gradient sums spill registers: slower, measured.)
+        constexpr int KG = 1;
+        auto kern = k_wire_adjoint_offsets_static<512, C, 64 * C, KG, true, 8, 8>;
         const size_t lds8 = static_lds_bytes(plan, C);
         set_lds(kern, lds8);
-        hipLaunchKernelGGL(kern, grid, dim3(64 * C), lds8, s, Gt, ldG, strideG, S, ldS, strideS, batch, groups,
-                           n_wires, n_imp, F, nyq, plan, R, dR, part, pstride, resp_scale, accumulate ? 1 : 0);
-        e = hipGetLastError();
+        const dim3 grid8((unsigned)(((F + C - 1) / C) * ((n_imp + KG - 1) / KG)));
+        hipLaunchKernelGGL(kern, grid8, dim3(64 * C), lds8, s, Gt, ldG, strideG, S, ldS, strideS, batch, n_wires,
+                           n_imp, F, nyq, plan, R, dR, resp_scale, accumulate ? 1 : 0);
+        return hipGetLastError();
     }
+    dim3 grid((unsigned)(((F + C - 1) / C) * groups));
+    hipError_t e = hipErrorInvalidValue;
     const size_t lds = ((size_t)plan.n * C + plan.n) * sizeof(float2);
 #define LAR_WADJI(V, NT)                                                                                \
     {                                                                                                   \
@@ -1526,8 +1537,7 @@ hipError_t launch_wire_adjoint_items(const float2* Gt, int64_t ldG, int64_t stri
                            pstride, resp_scale, accumulate ? 1 : 0);                                    \
         e = hipGetLastError();                                                                          \
     }
-    if (plan_is_888(plan)) {
-    } else if (nw_fft <= 128) LAR_WADJI(2, 512)
+    if (nw_fft <= 128) LAR_WADJI(2, 512)
     else if (nw_fft <= 256) LAR_WADJI(4, 512)
     else if (nw_fft <= 512) LAR_WADJI(8, 512)
     else if (nw_fft <= 1024) LAR_WADJI(8, 1024)
