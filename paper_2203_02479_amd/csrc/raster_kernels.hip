@@ -927,9 +927,10 @@ __device__ __forceinline__ bool queue_write(DeferredBin* queue, int part, unsign
 }
 
 // 5 waves per SIMD: the sampler stages fit 96 VGPRs, and the LDS of a
-// workgroup (about 29 KB) lets 5 workgroups share a CU
+// workgroup (about 29 KB with a 512-float tile) lets 5 workgroups share a
+// CU; with a 768-float tile (about 33 KB) 4 do
 template <int MODE, int TILE>
-__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(TILE > 640 ? 4 : 5, 8)))
 void k_raster(RasterItem one, const RasterItem* __restrict__ items, int n_items, int64_t total_sub,
               RasterWs* __restrict__ ws, uint8_t* __restrict__ flags, DeferredBin* __restrict__ queue,
               unsigned long long cap) {
