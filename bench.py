@@ -128,6 +128,26 @@ def copy_calibration(torch):
     log(f"calibration: copied {n * 4} bytes 5 times")
 
 
+def atomic_peak(torch, lar, reps=20):
+    """Peak rate of scattered 64-float wave atomics (the raster's tile-flush
+    access) over a buffer the size of the collection plane's impact-resolved
+    raster target (4800 rows x 6000 ticks)."""
+    n = 4800 * 6000
+    buf = torch.zeros(n, device="cuda")
+    n_seg = 1 << 22
+    ms = time_reps(torch, lambda: lar.atomic_probe(buf, n_seg), 3, reps)
+    med_ms = float(statistics.median(ms))
+    out = {"segments": n_seg, "floats": n_seg * 64, "buffer_bytes": n * 4, "reps": reps,
+           "median_ms": round(med_ms, 4), "wave_atomics_per_s": n_seg / med_ms * 1e3,
+           "float_atomics_per_s": n_seg * 64 / med_ms * 1e3}
+    torch.cuda.synchronize()
+    total = float(buf.double().sum().item())
+    expect = float(n_seg) * 64 * (reps + 3)
+    if total != expect:
+        raise RuntimeError(f"atomic probe: buffer sum {total} != {expect}")
+    return out
+
+
 def time_reps(torch, fn, warmup, reps, stream=None):
     """Per-repetition times (ms) of fn() with HIP events on `stream`."""
     stream = stream or torch.cuda.current_stream()
@@ -468,6 +488,8 @@ def main():
     ap.add_argument("--skip-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT schedules")
     ap.add_argument("--calib", action="store_true", help="run the copy-kernel counter calibration only")
+    ap.add_argument("--atomic-peak", action="store_true",
+                    help="time the scattered float-atomic probe only and print its JSON")
     ap.add_argument("--leg", choices=["fwd_bwd", "batched", "three_plane"], default=None,
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -487,6 +509,9 @@ def main():
     torch.cuda.set_device(0)
     if args.calib:
         copy_calibration(torch)
+        return
+    if args.atomic_peak:
+        print(json.dumps({"atomic_peak": atomic_peak(torch, lar)}), flush=True)
         return
     legs = {"fwd_bwd": leg_fwd_bwd, "batched": leg_batched, "three_plane": leg_three_plane}
     if args.leg:

@@ -451,6 +451,15 @@ int lar_schedule_candidates(const lar_plane *plane, lar_schedule *out, int32_t c
  * pass NULL to stop.  Recording adds no synchronisation. */
 int lar_set_stage_events(void *const *events, int32_t n_events);
 
+/* Measurement aid (no paper counterpart): the peak rate of the global float
+ * atomics the raster's tile flushes issue, for comparing the mean raster,
+ * which they bound, against it.  Adds 1.0f to n_segments segments of 64
+ * consecutive floats of buf (device, n_floats >= 64, 256-byte aligned), one
+ * wave per segment, at segment slots spread over the buffer by a hash; buf
+ * keeps the sums.  Asynchronous on stream.  LAR_EINVAL for a null or
+ * misaligned buf, n_floats < 64 or n_segments < 0. */
+int lar_atomic_probe(float *buf, int64_t n_floats, int64_t n_segments, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,11 @@
 
 using namespace lar;
 
+namespace lar {
+// probe_kernels.hip: n_seg scattered 64-float atomic segments into buf.
+hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipStream_t s);
+}
+
 static thread_local int g_last_hip = 0;
 static thread_local hipEvent_t g_stage_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
@@ -96,6 +101,12 @@ const char* lar_status_str(int s) {
 }
 
 int lar_last_hip_error(void) { return g_last_hip; }
+
+int lar_atomic_probe(float* buf, int64_t n_floats, int64_t n_segments, void* stream) {
+    if (!buf || n_floats < 64 || n_segments < 0 || reinterpret_cast<uintptr_t>(buf) % 256) return LAR_EINVAL;
+    LAR_TRY(launch_atomic_probe(buf, n_floats, n_segments, (hipStream_t)stream));
+    return LAR_OK;
+}
 
 int lar_set_stage_events(void* const* events, int32_t n_events) {
     if (!events) {

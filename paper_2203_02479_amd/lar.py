@@ -110,6 +110,7 @@ SIGNATURES = {
     "lar_batch_destroy": ([_VP], ctypes.c_int),
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_depos_nonfinite": ([_P(lar_depos), _VP, _VP], ctypes.c_int),
+    "lar_atomic_probe": ([_VP, ctypes.c_int64, ctypes.c_int64, _VP], ctypes.c_int),
     "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_get": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_set": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
@@ -225,6 +226,14 @@ def depos_nonfinite(depos: DeviceDepos, out=None, stream=None):
     ds = depos.struct()
     _check(_lib().lar_depos_nonfinite(ctypes.byref(ds), _ptr(out), _stream(stream)), "lar_depos_nonfinite")
     return out
+
+
+def atomic_probe(buf, n_segments, stream=None):
+    """Peak-rate probe of the raster's global float atomics: adds 1 to
+    n_segments scattered 64-float segments of buf (a float32 device tensor)."""
+    if buf.dtype != torch.float32:
+        raise TypeError("float32 buffer expected")
+    _check(_lib().lar_atomic_probe(_ptr(buf), buf.numel(), int(n_segments), _stream(stream)), "lar_atomic_probe")
 
 
 def raster_workspace(plane, n_depos, fluct) -> int:

@@ -170,6 +170,15 @@ def test_nonfinite_counter_host_side_errors(lar):
     assert L.lar_depos_nonfinite(ctypes.byref(huge), one, None) == lar.LAR_ESIZE
 
 
+def test_atomic_probe_host_side_errors(lar):
+    L = lar.lib()
+    al = ctypes.c_void_p(256)
+    assert L.lar_atomic_probe(None, 64, 1, None) == lar.LAR_EINVAL
+    assert L.lar_atomic_probe(ctypes.c_void_p(260), 64, 1, None) == lar.LAR_EINVAL
+    assert L.lar_atomic_probe(al, 63, 1, None) == lar.LAR_EINVAL
+    assert L.lar_atomic_probe(al, 64, -1, None) == lar.LAR_EINVAL
+
+
 def test_schedule_registry_host_side(lar):
     P = inputs.cfg1_plane()
     d = lar.schedule_default(P)

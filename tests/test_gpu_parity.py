@@ -119,6 +119,25 @@ def test_nonfinite_depos_counter():
     assert lar.depos_nonfinite(lar.DeviceDepos.from_host(empty), out).item() == 0
 
 
+def test_atomic_probe_counts():
+    """The float-atomic rate probe adds exactly 1 to every float of each
+    hashed 64-float segment, per call, and leaves the tail past the last
+    whole segment alone."""
+    torch, lar = _torch(), _lar()
+    n, n_seg = 64 * 1000 + 17, 50_000
+    buf = torch.zeros(n, device="cuda")
+    lar.atomic_probe(buf, n_seg)
+    lar.atomic_probe(buf, n_seg)
+    sg = np.arange(n_seg, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        slot = ((sg * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(17)) % np.uint64(1000)
+    expect = np.zeros(n, np.float32)
+    expect[:64000] = np.repeat(2.0 * np.bincount(slot.astype(np.int64), minlength=1000), 64)
+    assert np.array_equal(buf.cpu().numpy(), expect)
+    lar.atomic_probe(buf, 0)
+    torch.cuda.synchronize()
+
+
 def test_raster_accumulates():
     torch, lar = _torch(), _lar()
     ev = inputs.cfg0_event()
