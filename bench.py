@@ -284,6 +284,26 @@ def leg_three_plane(args, torch, lar, inputs, np):
 
     reps = max(10, args.steps // 2)
     ms = med(time_reps(torch, three, 3, reps))
+    # per-stage times of the U plane (800 wires, Wf 864): the FFT stages at
+    # this shape against their algorithmic bytes
+    stream = torch.cuda.current_stream()
+    stage = [[torch.cuda.Event(enable_timing=True) for _ in STAGES] for _ in range(reps)]
+    start = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for row in stage:
+        for e in row:
+            e.record(stream)
+    for _ in range(3):
+        three()
+    torch.cuda.synchronize()
+    for i in range(reps):
+        start[i].record(stream)
+        lar.set_stage_events(stage[i])
+        lar.sim_plane(planes[0], Ds[0], inputs.NSIGMA, (1, seed, 0, 0), resps[0], waves[0], wss[0], stream)
+    lar.set_stage_events(None)
+    torch.cuda.synchronize()
+    per_u = {n: med([(start[i] if s_ == 0 else stage[i][s_ - 1]).elapsed_time(stage[i][s_]) for i in range(reps)])
+             for s_, n in enumerate(STAGES)}
+    roof_u = fft_roofline(algorithmic_bytes(planes[0]), per_u)
     # the same event as a 3-item batch plan (U, V share a type)
     del wss
     types = [planes[0], planes[2]]
@@ -311,7 +331,9 @@ def leg_three_plane(args, torch, lar, inputs, np):
             "plane_frames_per_s": round(3e3 / ms, 2),
             "batch_plan_ms_per_event": round(ms_b, 4),
             "batch_plan_depos_per_s": round(n_depo / (ms_b * 1e-3), 1),
-            "fft_algorithmic_bytes": int(fft_bytes)}
+            "fft_algorithmic_bytes": int(fft_bytes),
+            "u_plane_kernel_ms": {k: round(v, 5) for k, v in per_u.items()},
+            "roofline_fft_u_plane": roof_u}
 
 
 # ------------------------------------------------------------------ batch
