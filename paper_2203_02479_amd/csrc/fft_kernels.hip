@@ -843,8 +843,7 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
     tile_item(xcd_tile(blockIdx.x, gridDim.x), (F + C - 1) / C, batch, C, tile, item);
     S += (int64_t)item * strideS;
     M += (int64_t)item * strideM;
-    Fft fx(lds, plan, threadIdx.x);
-    const int j = fx.j, s = fx.s, f0 = tile * C;
+    const int j = threadIdx.x / C, s = threadIdx.x % C, f0 = tile * C;   // StaticFft's (j, s)
     const int f = min(f0 + s, F - 1);
     const bool f_ok = f0 + s < F;
     float2 v[R0], rr[R0], acc[R0];
@@ -871,8 +870,10 @@ void k_wire_static(const float2* __restrict__ S, int64_t ldS, int n_wires, int n
             rr[r] = Rk[(int64_t)p * F + f];
         }
     };
+    // the first gathers are in flight while the twiddle table is built
     gather_s(0);
     if (PREF) gather_r(0);
+    Fft fx(lds, plan, threadIdx.x);
     for (int k = 0; k < n_imp; ++k) {
         float2 x[R0];
 #pragma unroll
