@@ -14,7 +14,8 @@ Extra objects of the same JSON line:
                normal approximation instead of the binomial;
   three_plane  one event of the three-plane readout (U, V: 800 wires,
                bipolar, Wf 864; W: 480 wires; 2M depos incl. 100k points),
-               three lar_sim_plane calls, and as a 3-item batch plan;
+               three lar_sim_plane calls, and as a 3-item batch plan; the
+               U plane's per-stage times and FFT roofline;
   batched      64 events x 3 planes with log-uniform depo counts: the batch
                plan (waves bounded by a workspace budget, hipGraph) against
                192 sequential lar_sim_plane calls and against the streams
@@ -23,6 +24,10 @@ Extra objects of the same JSON line:
                forward + MSE + backward: 16 sequential autograd steps, and
                the batched forward + batched backward plan;
   cpu_baseline the FP64 oracle on the host's cores (and on one thread).
+
+Profiling aids (each prints its own JSON and exits): --calib (a 1 GiB copy
+for scaling the PMC byte counters), --atomic-peak (the peak rate of the
+raster's scattered float atomics), --leg NAME (one extra leg alone).
 """
 from __future__ import annotations
 
