@@ -27,7 +27,8 @@ Extra objects of the same JSON line:
 
 Profiling aids (each prints its own JSON and exits): --calib (a 1 GiB copy
 for scaling the PMC byte counters), --atomic-peak (the peak rate of the
-raster's scattered float atomics), --leg NAME (one extra leg alone).
+raster's scattered float atomics), --copy-floor (the memory floor of the
+time R2C's access pattern), --leg NAME (one extra leg alone).
 """
 from __future__ import annotations
 
@@ -150,6 +151,37 @@ def atomic_peak(torch, lar, reps=20):
     expect = float(n_seg) * 64 * (reps + 3)
     if total != expect:
         raise RuntimeError(f"atomic probe: buffer sum {total} != {expect}")
+    return out
+
+
+def copy_floor(torch, lar, reps=30):
+    """Memory floors of the time R2C's bytes at the collection plane's 4800
+    rows and the induction plane's 8000 rows (6000 ticks, Tf 6144): the
+    library's row-copy probe (the transform's grid and access pattern, no
+    transform) at 1-4 workgroups per CU, and a flat device copy of the same
+    byte count."""
+    out = {}
+    n_in, n_out, ld_out = 6000, 3073, 3088
+    for rows in (4800, 8000):
+        src = torch.randn(rows, n_in, device="cuda")
+        dst = torch.zeros(rows, 2 * ld_out, device="cuda")
+        nbytes = rows * (n_in * 4 + n_out * 8)
+        rec = {"bytes": nbytes}
+        for per in (1, 2, 3, 4):
+            ms = med(time_reps(torch, lambda: lar.row_copy_probe(src, dst, n_out, per), 3, reps))
+            rec[f"row_copy_{per}_per_cu_us"] = round(ms * 1e3, 2)
+            rec[f"row_copy_{per}_per_cu_gbs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+        if not torch.equal(dst[:, :n_in], src):
+            raise RuntimeError("row copy probe: output rows differ from the input rows")
+        half = nbytes // 2 // 4
+        a = torch.randn(half, device="cuda")
+        b = torch.empty_like(a)
+        ms = med(time_reps(torch, lambda: b.copy_(a), 3, reps))
+        rec["flat_copy_us"] = round(ms * 1e3, 2)
+        rec["flat_copy_gbs"] = round(2 * half * 4 / (ms * 1e-3) / 1e9, 1)
+        out[f"{rows}_rows"] = rec
+        del src, dst, a, b
+        torch.cuda.empty_cache()
     return out
 
 
@@ -517,6 +549,8 @@ def main():
     ap.add_argument("--calib", action="store_true", help="run the copy-kernel counter calibration only")
     ap.add_argument("--atomic-peak", action="store_true",
                     help="time the scattered float-atomic probe only and print its JSON")
+    ap.add_argument("--copy-floor", action="store_true",
+                    help="time the row-copy probe and a flat copy at the time R2C's byte counts and print their JSON")
     ap.add_argument("--leg", choices=["fwd_bwd", "batched", "three_plane"], default=None,
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -539,6 +573,9 @@ def main():
         return
     if args.atomic_peak:
         print(json.dumps({"atomic_peak": atomic_peak(torch, lar)}), flush=True)
+        return
+    if args.copy_floor:
+        print(json.dumps({"copy_floor": copy_floor(torch, lar)}), flush=True)
         return
     legs = {"fwd_bwd": leg_fwd_bwd, "batched": leg_batched, "three_plane": leg_three_plane}
     if args.leg:

@@ -460,6 +460,20 @@ int lar_set_stage_events(void *const *events, int32_t n_events);
  * misaligned buf, n_floats < 64 or n_segments < 0. */
 int lar_atomic_probe(float *buf, int64_t n_floats, int64_t n_segments, void *stream);
 
+/* Measurement aid (no paper counterpart): the memory floor of the time
+ * R2C's access pattern, for comparing that transform against it.  Copies
+ * n_rows rows with the transform's persistent grid (blocks_per_cu
+ * workgroups of 384 threads per compute unit, 1..16) and loads: input row
+ * r (device, n_in floats at in + r*ld_in; n_in even, 2..6144) is read as
+ * n_in/2 float pairs, and output row r (device, n_out complex values of 8
+ * bytes at out + r*ld_out complex; n_out 1..3073) receives pair k at
+ * element k for k < n_in/2, the last pair at the elements after it.  Both
+ * buffers 8-byte aligned, ld_in even, ld_in >= n_in, ld_out >= n_out.
+ * Asynchronous on stream.  LAR_EINVAL for arguments outside these ranges;
+ * nothing is launched for n_rows == 0. */
+int lar_row_copy_probe(const float *in, int64_t ld_in, int32_t n_in, int32_t n_rows, void *out, int64_t ld_out,
+                       int32_t n_out, int32_t blocks_per_cu, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

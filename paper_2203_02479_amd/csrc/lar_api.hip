@@ -14,6 +14,9 @@ using namespace lar;
 namespace lar {
 // probe_kernels.hip: n_seg scattered 64-float atomic segments into buf.
 hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipStream_t s);
+// probe_kernels.hip: the time R2C's row access pattern without the transform.
+hipError_t launch_row_copy_probe(const float* in, int64_t ld_in, int n_in, int nrows, float2* out, int64_t ld_out,
+                                 int n_out, int per_cu, hipStream_t s);
 }
 
 static thread_local int g_last_hip = 0;
@@ -105,6 +108,18 @@ int lar_last_hip_error(void) { return g_last_hip; }
 int lar_atomic_probe(float* buf, int64_t n_floats, int64_t n_segments, void* stream) {
     if (!buf || n_floats < 64 || n_segments < 0 || reinterpret_cast<uintptr_t>(buf) % 256) return LAR_EINVAL;
     LAR_TRY(launch_atomic_probe(buf, n_floats, n_segments, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+int lar_row_copy_probe(const float* in, int64_t ld_in, int32_t n_in, int32_t n_rows, void* out, int64_t ld_out,
+                       int32_t n_out, int32_t blocks_per_cu, void* stream) {
+    if (n_rows < 0 || blocks_per_cu < 1 || blocks_per_cu > 16) return LAR_EINVAL;
+    if (n_rows == 0) return LAR_OK;
+    if (!in || !out || n_in < 2 || (n_in & 1) || n_in > 6144 || n_out < 1 || n_out > 3073 || ld_in < n_in ||
+        ld_out < n_out || (ld_in & 1) || reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8)
+        return LAR_EINVAL;
+    LAR_TRY(launch_row_copy_probe(in, ld_in, n_in, n_rows, static_cast<float2*>(out), ld_out, n_out, blocks_per_cu,
+                                  (hipStream_t)stream));
     return LAR_OK;
 }
 

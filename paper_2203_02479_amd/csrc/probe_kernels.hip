@@ -1,9 +1,19 @@
-// probe_kernels.hip -- a measurement aid with no counterpart in the method:
-// the peak rate of the device-scope float atomics that the raster's tile
-// flushes issue (one wave writes 64 consecutive floats of the grid with one
-// atomic instruction).  Each wave adds 1.0f to one 64-float segment at a
-// slot spread over the buffer by a multiplicative hash, so the requests land
-// on every L2 channel and memory page the way scattered tile flushes do.
+// probe_kernels.hip -- measurement aids with no counterpart in the method.
+//
+//  k_atomic_probe  the peak rate of the device-scope float atomics that the
+//                  raster's tile flushes issue (one wave writes 64
+//                  consecutive floats of the grid with one atomic
+//                  instruction).  Each wave adds 1.0f to one 64-float
+//                  segment at a slot spread over the buffer by a
+//                  multiplicative hash, so the requests land on every L2
+//                  channel and memory page the way scattered tile flushes do.
+//  k_row_copy_probe  the memory floor of the time R2C's access pattern: the
+//                  same persistent grid of 384-thread workgroups, rows read
+//                  as float pairs with the next row's loads in flight, rows
+//                  of complex values written at a padded pitch, and no
+//                  transform in between.
+#include <algorithm>
+
 #include "lar_internal.hpp"
 
 namespace lar {
@@ -28,6 +38,49 @@ hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipS
     const int64_t blocks = (n_seg + 3) / 4, cap = 64 * (int64_t)device_cus();
     hipLaunchKernelGGL(k_atomic_probe, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, s, buf, slots,
                        n_seg);
+    return hipGetLastError();
+}
+
+// Row r: pairs k < n_in/2 of the input row (k = tid + 384 i, i < 8) go to
+// element k of the output row; elements n_in/2 .. n_out-1 repeat the last
+// pair (the writes the transform would make there).  n_in <= 6144 and
+// n_out <= 3073 (checked by the caller): every read index is clamped into
+// the row and every write index is below n_out.
+__global__ __launch_bounds__(384) void k_row_copy_probe(const float* __restrict__ in, int64_t ld_in, int n_in,
+                                                        int nrows, float2* __restrict__ out, int64_t ld_out,
+                                                        int n_out) {
+    const int tid = threadIdx.x, last = (n_in >> 1) - 1;
+    float2 v[8], vl = make_float2(0.f, 0.f);
+    int row = blockIdx.x;
+    auto issue = [&](int r) {
+        const float2* x2 = reinterpret_cast<const float2*>(in + (int64_t)r * ld_in);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = x2[min(tid + i * 384, last)];
+        if (tid == 0) vl = x2[last];   // element 3072 (n_out = 3073)
+    };
+    if (row < nrows) issue(row);
+    for (; row < nrows; row += gridDim.x) {
+        float2 u[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) u[i] = v[i];
+        const float2 ul = vl;
+        if (row + (int)gridDim.x < nrows) issue(row + gridDim.x);
+        float2* y = out + (int64_t)row * ld_out;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = tid + i * 384;
+            if (k < n_out) y[k] = u[i];
+        }
+        if (tid == 0 && n_out > 3072) y[3072] = ul;
+    }
+}
+
+hipError_t launch_row_copy_probe(const float* in, int64_t ld_in, int n_in, int nrows, float2* out, int64_t ld_out,
+                                 int n_out, int per_cu, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(nrows, (int64_t)per_cu * device_cus());
+    hipLaunchKernelGGL(k_row_copy_probe, dim3((unsigned)g), dim3(384), 0, s, in, ld_in, n_in, nrows, out, ld_out,
+                       n_out);
     return hipGetLastError();
 }
 

@@ -111,6 +111,8 @@ SIGNATURES = {
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_depos_nonfinite": ([_P(lar_depos), _VP, _VP], ctypes.c_int),
     "lar_atomic_probe": ([_VP, ctypes.c_int64, ctypes.c_int64, _VP], ctypes.c_int),
+    "lar_row_copy_probe": ([_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_int64, ctypes.c_int32,
+                            ctypes.c_int32, _VP], ctypes.c_int),
     "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_get": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
     "lar_schedule_set": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
@@ -234,6 +236,20 @@ def atomic_probe(buf, n_segments, stream=None):
     if buf.dtype != torch.float32:
         raise TypeError("float32 buffer expected")
     _check(_lib().lar_atomic_probe(_ptr(buf), buf.numel(), int(n_segments), _stream(stream)), "lar_atomic_probe")
+
+
+def row_copy_probe(src, dst, n_out, blocks_per_cu=2, stream=None):
+    """Memory-floor probe of the time R2C's access pattern: every row of src
+    (float32 [rows][n_in]) read as float pairs, the first n_out complex
+    values of every row of dst (float32 [rows][2 ld_out], complex values as
+    float pairs, n_out <= ld_out) written."""
+    if src.dtype != torch.float32 or dst.dtype != torch.float32 or src.dim() != 2 or dst.dim() != 2:
+        raise TypeError("2-D float32 tensors expected")
+    if src.shape[0] != dst.shape[0] or dst.shape[1] % 2:
+        raise ValueError("row counts differ or odd output width")
+    rows, n_in, ld_out = src.shape[0], src.shape[1], dst.shape[1] // 2
+    _check(_lib().lar_row_copy_probe(_ptr(src), n_in, n_in, rows, _ptr(dst), ld_out, int(n_out),
+                                     int(blocks_per_cu), _stream(stream)), "lar_row_copy_probe")
 
 
 def raster_workspace(plane, n_depos, fluct) -> int:

@@ -179,6 +179,18 @@ def test_atomic_probe_host_side_errors(lar):
     assert L.lar_atomic_probe(al, 64, -1, None) == lar.LAR_EINVAL
 
 
+def test_row_copy_probe_host_side_errors(lar):
+    L = lar.lib()
+    a = ctypes.c_void_p(256)
+    ok = (a, 6000, 6000, 4, a, 3088, 3073, 2, None)
+    assert L.lar_row_copy_probe(a, 6000, 6000, 0, None, 0, 0, 2, None) == lar.LAR_OK   # nothing to copy
+    for i, bad in ((0, None), (1, 5999), (2, 6001), (2, 6146), (3, -1), (4, None), (5, 3000), (6, 3074), (6, 0),
+                   (7, 0), (7, 17), (0, ctypes.c_void_p(260)), (4, ctypes.c_void_p(260))):
+        args = list(ok)
+        args[i] = bad
+        assert L.lar_row_copy_probe(*args) == lar.LAR_EINVAL, (i, bad)
+
+
 def test_schedule_registry_host_side(lar):
     P = inputs.cfg1_plane()
     d = lar.schedule_default(P)

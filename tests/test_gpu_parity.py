@@ -138,6 +138,26 @@ def test_atomic_probe_counts():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("rows,n_in,n_out,per_cu", [(1, 6000, 3073, 1), (37, 6000, 3073, 2), (600, 1024, 513, 3),
+                                                    (5, 6144, 3073, 4)])
+def test_row_copy_probe_rows(rows, n_in, n_out, per_cu):
+    """The row-copy probe writes pair k of each input row to element k of
+    its output row (the last pair repeated past n_in/2) and nothing past
+    n_out."""
+    torch, lar = _torch(), _lar()
+    src = torch.randn(rows, n_in, device="cuda")
+    dst = torch.full((rows, 2 * n_out + 6), -7.0, device="cuda")
+    lar.row_copy_probe(src, dst, n_out, per_cu)
+    torch.cuda.synchronize()
+    got, ref = dst.cpu().numpy(), src.cpu().numpy()
+    half = min(n_in // 2, n_out)
+    assert np.array_equal(got[:, :2 * half], ref[:, :2 * half])
+    if n_out > n_in // 2:
+        tail = got[:, 2 * half:2 * n_out].reshape(rows, -1, 2)
+        assert np.array_equal(tail, np.broadcast_to(ref[:, None, n_in - 2:n_in], tail.shape))
+    assert (got[:, 2 * n_out:] == -7.0).all()
+
+
 def test_raster_accumulates():
     torch, lar = _torch(), _lar()
     ev = inputs.cfg0_event()
