@@ -14,10 +14,18 @@
 // item of the wave together on one XCD, so the tile's response slabs come
 // from that XCD's L2.
 //
+// With more than one wave the grids are double-buffered (waves alternate
+// between two grid regions) and the FFT stages of each wave run on a second
+// stream: wave w's memory-bound transforms overlap wave w+1's ALU-bound
+// raster.  The raster of wave w+2 waits for wave w's time R2C (the last
+// reader of its grid region); the FFT stages of successive waves, which
+// share the spectrum regions, stay in order on their stream.  A run forks
+// the second stream from the caller's and joins it back at the end.
+//
 // Workspace layout (all 256-byte aligned):
 //   item records in wave order | raster item table | wave-local sub-chunk
-//   prefix | per-type plane constants | output row offsets | arena | raster
-//   queue
+//   prefix | per-type plane constants | output row offsets | arena | second
+//   grid region (more than one wave) | raster queue
 #include <limits.h>
 #include <math.h>
 
@@ -58,7 +66,7 @@ struct DevItem {
     uint32_t event, plane;
     int64_t depo_offset, n_depos;
     int32_t wave_first;         // index (wave order) of the first item of its wave
-    int32_t pad;
+    int32_t buf;                // grid region of its wave: 0 (the arena) or 1
 };
 
 // Per-type constants the table kernel needs.
@@ -66,6 +74,7 @@ struct DevType {
     RasterArgs proto;           // geometry and fluctuation; event and plane set per item
     int64_t grid_stride;        // floats between the grids of consecutive slots
     float* grid0;               // grid of slot 0 in the arena
+    float* grid1;               // grid of slot 0 in the second grid region
 };
 
 struct Wave {
@@ -74,12 +83,12 @@ struct Wave {
 };
 
 struct Layout {
-    size_t items, table, prefix, types, rowoff, arena, raster, total;
+    size_t items, table, prefix, types, rowoff, arena, grid1, raster, total;
     int K = 0;                                  // items per wave
     std::vector<int> order;                     // wave order -> item index
     std::vector<Wave> waves;
     std::vector<size_t> gsz, ssz, msz;          // per type, per slot
-    size_t arena_bytes = 0, raster_bytes = 0;
+    size_t arena_bytes = 0, grid1_bytes = 0, raster_bytes = 0;
     int64_t total_rows_out = 0;
 };
 
@@ -122,8 +131,10 @@ void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, i
     L.ssz.assign(n_types, 0);
     L.msz.assign(n_types, 0);
     L.arena_bytes = 0;
+    L.grid1_bytes = 0;
     L.raster_bytes = 0;
     L.total_rows_out = 0;
+    size_t grids_max = 0;
     int64_t max_sub = 0, max_depos = 0;
     for (int t = 0; t < n_types; ++t) {
         const lar_plane& p = planes[t];
@@ -150,9 +161,11 @@ void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, i
             max_sub = std::max(max_sub, w.total_sub);
             max_depos = std::max(max_depos, w.n_depos);
             L.arena_bytes = std::max(L.arena_bytes, (L.gsz[t] + L.ssz[t] + L.msz[t]) * (size_t)w.count);
+            grids_max = std::max(grids_max, L.gsz[t] * (size_t)w.count);
             L.waves.push_back(w);
         }
     }
+    if (L.waves.size() > 1) L.grid1_bytes = grids_max;   // double-buffered grids
     L.raster_bytes = raster_ws_for(fluct, max_sub, max_depos);
     size_t off = 0;
     L.items = off;  off += al(sizeof(DevItem) * (size_t)n_items);
@@ -161,6 +174,7 @@ void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, i
     L.types = off;  off += al(sizeof(DevType) * (size_t)n_types);
     L.rowoff = off; off += al(sizeof(int64_t) * (size_t)L.total_rows_out);
     L.arena = off;  off += L.arena_bytes;
+    L.grid1 = off;  off += L.grid1_bytes;
     L.raster = off; off += L.raster_bytes;
     L.total = off;
 }
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(kTableThreads) void k_batch_table(const DevItem* __
         r.x = depos.x + d.depo_offset;
         r.st = depos.sigma_t + d.depo_offset;
         r.sx = depos.sigma_x + d.depo_offset;
-        r.grid = T.grid0 + (int64_t)d.slot * T.grid_stride;
+        r.grid = (d.buf ? T.grid1 : T.grid0) + (int64_t)d.slot * T.grid_stride;
         r.n = d.n_depos;
         r.sub_begin = prefix[i] - prefix[d.wave_first];
         out[i] = r;
@@ -224,9 +238,15 @@ __global__ __launch_bounds__(kTableThreads) void k_batch_table(const DevItem* __
 }  // namespace
 
 struct lar_batch {
-    std::vector<std::function<hipError_t(hipStream_t)>> steps;
+    // each step enqueues on the main stream or on the FFT stream
+    std::vector<std::function<hipError_t(hipStream_t, hipStream_t)>> steps;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // second stream of an eager run (default priority) and the events that
+    // order the two streams: fork, join, raster done, time R2C done (by
+    // wave parity)
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_rast = nullptr, ev_r2c[2] = {nullptr, nullptr};
     // for the backward pass (mean path only)
     int mode = 0;
     std::vector<lar_plane> planes;
@@ -236,6 +256,7 @@ struct lar_batch {
     std::vector<RasterArgs> proto;       // per type
     lar_depos depos{};
     char* arena = nullptr;
+    char* grid1 = nullptr;               // second grid region (more than one wave), else null
     const RasterItem* dtab = nullptr;
     const int64_t* drow = nullptr;
     const DevItem* ditp = nullptr;
@@ -267,10 +288,16 @@ RasterArgs args_of(const lar_plane& p, float nsigma, const lar_fluct* fluct) {
     return a;
 }
 
-// Largest wave size whose layout fits in ws_bytes (0 if none does).
+// Largest wave size whose layout fits in ws_bytes (0 if none does).  Every
+// type in one wave is tried first: below that size the largest type takes
+// two waves or more, the layout holds the second grid region, and its size
+// grows with the wave size, so the rest is a bisection.
 int fit_waves(const lar_plane* planes, int n_types, const lar_batch_item* items, int n_items,
               const lar_fluct* fluct, size_t ws_bytes, Layout& L) {
-    int lo = 1, hi = max_type_count(items, n_items, n_types), best = 0;
+    const int m = max_type_count(items, n_items, n_types);
+    layout(planes, n_types, items, n_items, fluct, m, L);
+    if (L.total <= ws_bytes) return m;
+    int lo = 1, hi = m - 1, best = 0;
     while (lo <= hi) {
         const int mid = lo + (hi - lo) / 2;
         layout(planes, n_types, items, n_items, fluct, mid, L);
@@ -283,6 +310,24 @@ int fit_waves(const lar_plane* planes, int n_types, const lar_batch_item* items,
     }
     if (best) layout(planes, n_types, items, n_items, fluct, best, L);
     return best;
+}
+
+// Frees a plan and the HIP objects it owns (any of them may be null).
+void release(lar_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev_rast, b->ev_r2c[0], b->ev_r2c[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (b->s2) (void)hipStreamDestroy(b->s2);
+    delete b;
+}
+
+// fork: s2 waits for what s has enqueued so far; join: s waits for s2.
+hipError_t fork_join(lar_batch* b, hipStream_t s, hipStream_t s2, bool fork) {
+    hipEvent_t e = fork ? b->ev_fork : b->ev_join;
+    hipError_t r = hipEventRecord(e, fork ? s : s2);
+    return r == hipSuccess ? hipStreamWaitEvent(fork ? s2 : s, e, 0) : r;
 }
 
 }  // namespace
@@ -337,12 +382,14 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         dty[t].proto = args_of(planes[t], nsigma, fluct);
         dty[t].grid_stride = (int64_t)(L.gsz[t] / sizeof(float));
         dty[t].grid0 = reinterpret_cast<float*>(W + L.arena);
+        dty[t].grid1 = reinterpret_cast<float*>(W + (L.grid1_bytes ? L.grid1 : L.arena));
     }
     std::vector<int64_t> rowoff;
     rowoff.reserve(L.total_rows_out);
     std::vector<int64_t> row0;
     bool even = true;
-    for (const Wave& w : L.waves) {
+    for (size_t wi = 0; wi < L.waves.size(); ++wi) {
+        const Wave& w = L.waves[wi];
         row0.push_back((int64_t)rowoff.size());
         for (int j = 0; j < w.count; ++j) {
             const int i = w.first + j;
@@ -355,7 +402,7 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
             d.depo_offset = it.depo_offset;
             d.n_depos = it.n_depos;
             d.wave_first = w.first;
-            d.pad = 0;
+            d.buf = (L.grid1_bytes && (wi % 2)) ? 1 : 0;
             const lar_plane& p = planes[it.plane_type];
             for (int r = 0; r < p.n_wires; ++r) {
                 const int64_t o = it.wave_offset + (int64_t)r * p.n_ticks;
@@ -380,6 +427,7 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
     for (int t = 0; t < n_types; ++t) b->proto.push_back(dty[t].proto);
     b->depos = *depos;
     b->arena = W + L.arena;
+    b->grid1 = L.grid1_bytes ? W + L.grid1 : nullptr;
     b->dtab = reinterpret_cast<const RasterItem*>(W + L.table);
     b->drow = reinterpret_cast<const int64_t*>(W + L.rowoff);
     b->row0 = row0;
@@ -390,18 +438,30 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
     b->gsz = L.gsz;
     b->ssz = L.ssz;
     b->msz = L.msz;
+    if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_rast, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_r2c[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_r2c[1], hipEventDisableTiming) != hipSuccess ||
+        (!use_graph && hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking) != hipSuccess)) {
+        release(b);
+        return LAR_EHIP;
+    }
 
-    // ---- the launch sequence
+    // ---- the launch sequence: the main stream s clears the grids and runs
+    // the rasters, the FFT stream s2 the transforms
     const DevItem* ditp = reinterpret_cast<const DevItem*>(W + L.items);
     const DevType* dtyp = reinterpret_cast<const DevType*>(W + L.types);
     RasterItem* dtab = reinterpret_cast<RasterItem*>(W + L.table);
     int64_t* dpre = reinterpret_cast<int64_t*>(W + L.prefix);
     const lar_depos dep = *depos;
-    b->steps.push_back([=](hipStream_t s) {
+    b->steps.push_back([=](hipStream_t s, hipStream_t) {
         hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableThreads), 0, s, ditp, dtyp, n_items, dep, dtab,
                            dpre);
         return hipGetLastError();
     });
+    const bool dbl = L.grid1_bytes > 0;
+    const hipEvent_t ev_rast = b->ev_rast;
     void* rws = W + L.raster;
     const size_t rws_bytes = L.raster_bytes;
     for (size_t wi = 0; wi < L.waves.size(); ++wi) {
@@ -410,7 +470,8 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         const lar_plane p = planes[t];
         const int64_t ld = spec_ld_of(p);
         const int rows = p.n_wires * p.n_imp;
-        float* g = reinterpret_cast<float*>(W + L.arena);
+        float* g = reinterpret_cast<float*>(W + ((dbl && (wi % 2)) ? L.grid1 : L.arena));
+        const hipEvent_t ev_r2c = b->ev_r2c[wi % 2];
         float2* S = reinterpret_cast<float2*>(W + L.arena + L.gsz[t] * k);
         float2* M = reinterpret_cast<float2*>(W + L.arena + (L.gsz[t] + L.ssz[t]) * k);
         const int64_t gstride = (int64_t)(L.gsz[t] / sizeof(float));
@@ -423,49 +484,60 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         const Sched sc = sched_for(p.n_wires, p.n_imp, p.n_ticks, p.nt_fft, p.nw_fft);
         const RasterItem* wtab = dtab + w.first;
         const RasterItem one{};
-        b->steps.push_back([=](hipStream_t s) { return launch_fill(g, gstride * k, s); });
+        // this grid region was last read by the time R2C of wave wi - 2
+        if (dbl && wi >= 2)
+            b->steps.push_back([=](hipStream_t s, hipStream_t) { return hipStreamWaitEvent(s, ev_r2c, 0); });
+        b->steps.push_back([=](hipStream_t s, hipStream_t) { return launch_fill(g, gstride * k, s); });
         if (w.total_sub > 0)
-            b->steps.push_back([=](hipStream_t s) {
+            b->steps.push_back([=](hipStream_t s, hipStream_t) {
                 return launch_raster_items(mode, one, wtab, k, w.total_sub, rws, rws_bytes, s, nullptr,
                                            sc.raster_tile);
             });
+        b->steps.push_back([=](hipStream_t s, hipStream_t s2) {
+            hipError_t e = hipEventRecord(ev_rast, s);
+            return e == hipSuccess ? hipStreamWaitEvent(s2, ev_rast, 0) : e;
+        });
         // grids of a wave are gstride floats apart: one launch when unpadded
         if (gstride == (int64_t)rows * p.n_ticks && sstride == (int64_t)rows * ld) {
-            b->steps.push_back([=](hipStream_t s) {
-                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s, sc.row_threads,
+            b->steps.push_back([=](hipStream_t, hipStream_t s2) {
+                return launch_r2c_rows(g, p.n_ticks, p.n_ticks, rows * k, p.nt_fft, S, ld, s2, sc.row_threads,
                                        sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
-                b->steps.push_back([=](hipStream_t s) {
+                b->steps.push_back([=](hipStream_t, hipStream_t s2) {
                     return launch_r2c_rows(g + r * gstride, p.n_ticks, p.n_ticks, rows, p.nt_fft, S + r * sstride,
-                                           ld, s, sc.row_threads, sc.row_order);
+                                           ld, s2, sc.row_threads, sc.row_order);
                 });
         }
-        b->steps.push_back([=](hipStream_t s) {
-            return launch_wire_fused(S, ld, p.n_wires, p.n_imp, p.nw_fft, F, R, M, ld, s, k, sstride, mstride,
+        if (dbl) b->steps.push_back([=](hipStream_t, hipStream_t s2) { return hipEventRecord(ev_r2c, s2); });
+        b->steps.push_back([=](hipStream_t, hipStream_t s2) {
+            return launch_wire_fused(S, ld, p.n_wires, p.n_imp, p.nw_fft, F, R, M, ld, s2, k, sstride, mstride,
                                      sc.wire_cols, sc.wire_threads, sc.wire_order);
         });
         if (mstride == (int64_t)p.n_wires * ld) {
-            b->steps.push_back([=](hipStream_t s) {
-                return launch_c2r_rows(M, ld, p.n_wires * k, p.nt_fft, wave, p.n_ticks, p.n_ticks, scale, s, ro,
+            b->steps.push_back([=](hipStream_t, hipStream_t s2) {
+                return launch_c2r_rows(M, ld, p.n_wires * k, p.nt_fft, wave, p.n_ticks, p.n_ticks, scale, s2, ro,
                                        even, sc.row_threads, sc.row_order);
             });
         } else {
             for (int r = 0; r < k; ++r)
-                b->steps.push_back([=](hipStream_t s) {
+                b->steps.push_back([=](hipStream_t, hipStream_t s2) {
                     return launch_c2r_rows(M + r * mstride, ld, p.n_wires, p.nt_fft, wave, p.n_ticks, p.n_ticks,
-                                           scale, s, ro + (int64_t)r * p.n_wires, even, sc.row_threads,
+                                           scale, s2, ro + (int64_t)r * p.n_wires, even, sc.row_threads,
                                            sc.row_order);
                 });
         }
     }
     if (use_graph) {
-        hipStream_t cs = nullptr;
-        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+        hipStream_t cs = nullptr, cs2 = nullptr;
+        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            for (auto& f : b->steps) ok = ok && f(cs) == hipSuccess;
+            ok = fork_join(b, cs, cs2, true) == hipSuccess;
+            for (auto& f : b->steps) ok = ok && f(cs, cs2) == hipSuccess;
+            ok = ok && fork_join(b, cs, cs2, false) == hipSuccess;
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &g);
             ok = ok && e == hipSuccess && g;
@@ -476,11 +548,10 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
                 (void)hipGraphDestroy(g);
             }
         }
+        if (cs2) (void)hipStreamDestroy(cs2);
         if (cs) (void)hipStreamDestroy(cs);
         if (!ok) {
-            if (b->exec) (void)hipGraphExecDestroy(b->exec);
-            if (b->graph) (void)hipGraphDestroy(b->graph);
-            delete b;
+            release(b);
             return LAR_EHIP;
         }
     }
@@ -505,8 +576,10 @@ int lar_batch_run(lar_batch* b, void* stream) {
         hipError_t e = hipGraphLaunch(b->exec, s);
         if (e != hipSuccess) return ((void)hipGetLastError(), LAR_EHIP);
     } else {
+        if (fork_join(b, s, b->s2, true) != hipSuccess) return LAR_EHIP;
         for (auto& f : b->steps)
-            if (f(s) != hipSuccess) return LAR_EHIP;
+            if (f(s, b->s2) != hipSuccess) return ((void)fork_join(b, s, b->s2, false), LAR_EHIP);
+        if (fork_join(b, s, b->s2, false) != hipSuccess) return LAR_EHIP;
     }
     b->kept_wave = (int)b->waves.size() - 1;
     return LAR_OK;
@@ -537,7 +610,8 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
         const lar_plane& p = b->planes[t];
         const int64_t ld = spec_ld_of(p);
         const int rows = p.n_wires * p.n_imp;
-        float* g = reinterpret_cast<float*>(b->arena);
+        // the grid region this wave's raster items point at
+        float* g = reinterpret_cast<float*>((b->grid1 && (wi % 2)) ? b->grid1 : b->arena);
         float2* S = reinterpret_cast<float2*>(b->arena + b->gsz[t] * k);
         float2* M = reinterpret_cast<float2*>(b->arena + (b->gsz[t] + b->ssz[t]) * k);
         const int64_t gstride = (int64_t)(b->gsz[t] / sizeof(float));
@@ -604,10 +678,7 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
 }
 
 int lar_batch_destroy(lar_batch* b) {
-    if (!b) return LAR_OK;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    delete b;
+    release(b);
     return LAR_OK;
 }
 
