@@ -325,7 +325,10 @@ typedef struct lar_batch lar_batch;    /* opaque plan */
 /* Workspace for waves of at most max_wave items per plane type (0: every
  * item of a type in one wave, the most the plan can use): item tables,
  * one wave's grids, time spectra and wire-pass outputs (an arena shared by
- * every wave), and the raster queue of the largest wave (fluct only).
+ * every wave), with more than one wave a second region of one wave's grids
+ * (waves alternate between the two, so that a wave's FFT stages overlap the
+ * next wave's raster), and the raster queue of the largest wave (fluct
+ * only).
  * lar_batch_workspace(...) = lar_batch_workspace_waves(..., 0, ...).
  * n_items < 2^27 (LAR_ESIZE otherwise). */
 int lar_batch_workspace_waves(const lar_plane *planes, int32_t n_types, const lar_batch_item *items,
@@ -336,19 +339,24 @@ int lar_batch_workspace(const lar_plane *planes, int32_t n_types, const lar_batc
 
 /* Build a plan for these exact device buffers: depos holds all items'
  * depos (concatenated), resp[t] the spectrum of plane type t, wave the
- * output.  The waves are as large as ws_bytes allows (LAR_EWORKSPACE when
- * not even one item per wave fits).  Uploads the tables to the workspace (a
- * synchronous copy) and, with use_graph, captures the whole sequence into a
- * hipGraph.  The contents of depos / resp may change between runs; their
- * addresses and the item counts may not.  Setup call: it allocates host
- * memory and the graph. */
+ * output.  The waves are as large as ws_bytes allows (every type in one
+ * wave when that fits; LAR_EWORKSPACE when not even one item per wave
+ * fits).  Uploads the tables to the workspace (a synchronous copy) and, with
+ * use_graph, captures the whole sequence into a hipGraph.  The contents of
+ * depos / resp may change between runs; their addresses and the item
+ * counts may not.  Setup call: it allocates host memory, the graph, the
+ * events that order the plan's two streams and (without use_graph) the
+ * second stream, all released by lar_batch_destroy. */
 int lar_batch_create(const lar_plane *planes, int32_t n_types, const float *const *resp,
                      const lar_depos *depos, float nsigma, const lar_fluct *fluct,
                      const lar_batch_item *items, int32_t n_items, float *wave, void *workspace,
                      size_t ws_bytes, int32_t use_graph, lar_batch **plan);
 /* The plan's wave count and largest wave (either pointer may be NULL). */
 int lar_batch_waves(const lar_batch *plan, int32_t *n_waves, int32_t *max_items);
-/* Run the plan on `stream` (one graph launch with use_graph). */
+/* Run the plan on `stream` (one graph launch with use_graph).  The FFT
+ * stages run on a second stream forked from `stream` and joined back before
+ * the call's work on `stream` ends, so later work on `stream` sees the
+ * waveforms. */
 int lar_batch_run(lar_batch *plan, void *stream);
 
 /* Backward of a mean-path plan (fluct NULL or mode 0; LAR_EINVAL
