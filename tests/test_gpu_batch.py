@@ -81,6 +81,28 @@ def test_batch_matches_single_plane_runs(mode, use_graph, max_wave):
     b.close()
 
 
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_runs_back_to_back(use_graph):
+    """Runs queued without a synchronisation between them: the FFT stages of
+    one run's last waves (on the plan's second stream) finish before the next
+    run clears the grid regions, so the last run's waveforms are exact."""
+    torch, lar, planes, resps, items, deps, cat, fl, total = _setup(fluct_mode=1)
+    D = lar.DeviceDepos.from_host(cat)
+    wave = torch.full((total,), -7.0, device="cuda")
+    ws = lar.workspace(lar.batch_workspace(planes, items, fl, max_wave=1))
+    b = lar.Batch(planes, resps, D, 3.0, fl, items, wave, ws, use_graph=use_graph)
+    assert b.waves()[0] == 9
+    ref = _reference(torch, lar, planes, resps, items, deps, fl, total)
+    for _ in range(4):
+        b.run()
+    torch.cuda.synchronize()
+    got = wave.cpu().numpy()
+    for (pt, e, pl, off, n, wo) in items:
+        sl = slice(wo, wo + planes[pt].n_wires * planes[pt].n_ticks)
+        assert np.array_equal(got[sl], ref[sl]), (e, pl)
+    b.close()
+
+
 def test_batch_with_empty_items_and_one_item():
     torch, lar, planes, resps, items, deps, cat, fl, total = _setup(n_events=2, sizes=[0, 1500, 0, 700, 0, 0])
     D = lar.DeviceDepos.from_host(cat)
