@@ -24,8 +24,9 @@
 //
 // Workspace layout (all 256-byte aligned):
 //   item records in wave order | raster item table | wave-local sub-chunk
-//   prefix | per-type plane constants | output row offsets | arena | second
-//   grid region (more than one wave) | raster queue
+//   prefix | per-type plane constants | output row offsets | arena (grid,
+//   spectrum and wire-output regions, each sized for the largest wave) |
+//   second grid region (more than one wave) | raster queue
 #include <limits.h>
 #include <math.h>
 
@@ -89,6 +90,7 @@ struct Layout {
     std::vector<Wave> waves;
     std::vector<size_t> gsz, ssz, msz;          // per type, per slot
     size_t arena_bytes = 0, grid1_bytes = 0, raster_bytes = 0;
+    size_t s_off = 0, m_off = 0;                // spectra and wire outputs within the arena
     int64_t total_rows_out = 0;
 };
 
@@ -134,7 +136,7 @@ void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, i
     L.grid1_bytes = 0;
     L.raster_bytes = 0;
     L.total_rows_out = 0;
-    size_t grids_max = 0;
+    size_t grids_max = 0, specs_max = 0, outs_max = 0;
     int64_t max_sub = 0, max_depos = 0;
     for (int t = 0; t < n_types; ++t) {
         const lar_plane& p = planes[t];
@@ -160,11 +162,18 @@ void layout(const lar_plane* planes, int n_types, const lar_batch_item* items, i
             }
             max_sub = std::max(max_sub, w.total_sub);
             max_depos = std::max(max_depos, w.n_depos);
-            L.arena_bytes = std::max(L.arena_bytes, (L.gsz[t] + L.ssz[t] + L.msz[t]) * (size_t)w.count);
             grids_max = std::max(grids_max, L.gsz[t] * (size_t)w.count);
+            specs_max = std::max(specs_max, L.ssz[t] * (size_t)w.count);
+            outs_max = std::max(outs_max, L.msz[t] * (size_t)w.count);
             L.waves.push_back(w);
         }
     }
+    // the arena's grid, spectrum and output regions are disjoint and sized for
+    // the largest wave: a wave's grids never overlap the spectra or outputs
+    // that an earlier wave's FFT stages may still be using on the FFT stream
+    L.s_off = grids_max;
+    L.m_off = grids_max + specs_max;
+    L.arena_bytes = grids_max + specs_max + outs_max;
     if (L.waves.size() > 1) L.grid1_bytes = grids_max;   // double-buffered grids
     L.raster_bytes = raster_ws_for(fluct, max_sub, max_depos);
     size_t off = 0;
@@ -268,6 +277,7 @@ struct lar_batch {
     int kept_wave = -1;
     std::vector<int64_t> row0;           // per wave: first output row in drow
     std::vector<size_t> gsz, ssz, msz;
+    size_t s_off = 0, m_off = 0;         // spectrum and output regions within the arena
 };
 
 namespace {
@@ -438,6 +448,8 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
     b->gsz = L.gsz;
     b->ssz = L.ssz;
     b->msz = L.msz;
+    b->s_off = L.s_off;
+    b->m_off = L.m_off;
     if (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_rast, hipEventDisableTiming) != hipSuccess ||
@@ -472,8 +484,8 @@ int lar_batch_create(const lar_plane* planes, int32_t n_types, const float* cons
         const int rows = p.n_wires * p.n_imp;
         float* g = reinterpret_cast<float*>(W + ((dbl && (wi % 2)) ? L.grid1 : L.arena));
         const hipEvent_t ev_r2c = b->ev_r2c[wi % 2];
-        float2* S = reinterpret_cast<float2*>(W + L.arena + L.gsz[t] * k);
-        float2* M = reinterpret_cast<float2*>(W + L.arena + (L.gsz[t] + L.ssz[t]) * k);
+        float2* S = reinterpret_cast<float2*>(W + L.arena + L.s_off);
+        float2* M = reinterpret_cast<float2*>(W + L.arena + L.m_off);
         const int64_t gstride = (int64_t)(L.gsz[t] / sizeof(float));
         const int64_t sstride = (int64_t)(L.ssz[t] / sizeof(float2));
         const int64_t mstride = (int64_t)(L.msz[t] / sizeof(float2));
@@ -612,8 +624,8 @@ int lar_batch_backward(lar_batch* b, const float* wave_grad, float* const* resp_
         const int rows = p.n_wires * p.n_imp;
         // the grid region this wave's raster items point at
         float* g = reinterpret_cast<float*>((b->grid1 && (wi % 2)) ? b->grid1 : b->arena);
-        float2* S = reinterpret_cast<float2*>(b->arena + b->gsz[t] * k);
-        float2* M = reinterpret_cast<float2*>(b->arena + (b->gsz[t] + b->ssz[t]) * k);
+        float2* S = reinterpret_cast<float2*>(b->arena + b->s_off);
+        float2* M = reinterpret_cast<float2*>(b->arena + b->m_off);
         const int64_t gstride = (int64_t)(b->gsz[t] / sizeof(float));
         const int64_t sstride = (int64_t)(b->ssz[t] / sizeof(float2));
         const int64_t mstride = (int64_t)(b->msz[t] / sizeof(float2));

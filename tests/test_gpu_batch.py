@@ -103,6 +103,41 @@ def test_batch_runs_back_to_back(use_graph):
     b.close()
 
 
+def test_batch_waves_of_unequal_size():
+    """Waves of unequal size and plane type (7 items of the larger type in
+    waves of 3, 3, 1, then 6 of the smaller in waves of 3, 3), so that a
+    wave's grids are larger than an earlier, smaller wave's: each wave's
+    grids, spectra and outputs keep regions of their own while the FFT
+    stages of earlier waves still run, and the waveforms match per-item
+    runs exactly."""
+    import torch
+    from paper_2203_02479_amd import lar
+    planes = [inputs.Plane(n_wires=40, n_ticks=700, kind="bipolar"),
+              inputs.Plane(n_wires=24, n_ticks=700, kind="unipolar")]
+    resps = [lar.spectrum_from_time(p, inputs.response_time(p.n_imp, p.half_w, 200, p.kind)) for p in planes]
+    items, deps, off, woff = [], [], 0, 0
+    for i, pt in enumerate([0] * 7 + [1] * 6):
+        d = inputs.random_depos(planes[pt], 1200 + 97 * i, seed=900 + i, margin=0.1)
+        items.append((pt, i, pt, off, len(d.q), woff))
+        deps.append(d)
+        off += len(d.q)
+        woff += planes[pt].n_wires * planes[pt].n_ticks
+    cat = inputs.Depos(*(np.concatenate([d.arrays()[k] for d in deps]) for k in range(5)))
+    fl = (1, 4242, 0, 0)
+    ref = _reference(torch, lar, planes, resps, items, deps, fl, woff)
+    D = lar.DeviceDepos.from_host(cat)
+    for use_graph in (True, False):
+        wave = torch.full((woff,), -7.0, device="cuda")
+        ws = lar.workspace(lar.batch_workspace(planes, items, fl, max_wave=3))
+        b = lar.Batch(planes, resps, D, 3.0, fl, items, wave, ws, use_graph=use_graph)
+        assert b.waves() == (5, 3)
+        for _ in range(3):
+            b.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(wave.cpu().numpy(), ref), use_graph
+        b.close()
+
+
 def test_batch_with_empty_items_and_one_item():
     torch, lar, planes, resps, items, deps, cat, fl, total = _setup(n_events=2, sizes=[0, 1500, 0, 700, 0, 0])
     D = lar.DeviceDepos.from_host(cat)
