@@ -27,7 +27,8 @@ Extra objects of the same JSON line:
 
 Profiling aids (each prints its own JSON and exits): --calib (a 1 GiB copy
 for scaling the PMC byte counters), --atomic-peak (the peak rate of the
-raster's scattered float atomics), --copy-floor (the memory floor of the
+raster's scattered float atomics), --philox-peak (the rate of its per-bin
+Philox draw), --copy-floor (the memory floor of the
 time R2C's access pattern), --leg NAME (one extra leg alone).
 """
 from __future__ import annotations
@@ -152,6 +153,22 @@ def atomic_peak(torch, lar, reps=20):
     if total != expect:
         raise RuntimeError(f"atomic probe: buffer sum {total} != {expect}")
     return out
+
+
+def philox_peak(torch, lar, reps=20):
+    """Rate of the raster's per-bin draw (one Philox4x32-10 block and its
+    52-bit uniform) with every CU full: 2048 threads per CU, 2^28 blocks."""
+    n_threads, n_blocks = 256 * 2048, 1 << 28
+    out = torch.empty(n_threads, dtype=torch.float64, device="cuda")
+    ms = med(time_reps(torch, lambda: lar.philox_probe(out, n_blocks), 3, reps))
+    mean = float(out.sum().item()) / n_blocks
+    if abs(mean - 0.5) > 1e-3:
+        raise RuntimeError(f"philox probe: mean uniform {mean}")
+    rate = n_blocks / (ms * 1e-3)
+    return {"blocks": n_blocks, "threads": n_threads, "reps": reps, "median_ms": round(ms, 4),
+            "blocks_per_s": rate, "ops_per_s": rate * OPS_PER_BIN,
+            "frac_of_valu_peak": round(rate * OPS_PER_BIN / (VALU_PEAK_GOPS * 1e9), 4),
+            "mean_uniform": mean}
 
 
 def copy_floor(torch, lar, reps=30):
@@ -549,6 +566,8 @@ def main():
     ap.add_argument("--calib", action="store_true", help="run the copy-kernel counter calibration only")
     ap.add_argument("--atomic-peak", action="store_true",
                     help="time the scattered float-atomic probe only and print its JSON")
+    ap.add_argument("--philox-peak", action="store_true",
+                    help="time the Philox-block probe (the raster's per-bin draw) and print its JSON")
     ap.add_argument("--copy-floor", action="store_true",
                     help="time the row-copy probe and a flat copy at the time R2C's byte counts and print their JSON")
     ap.add_argument("--leg", choices=["fwd_bwd", "batched", "three_plane"], default=None,
@@ -573,6 +592,9 @@ def main():
         return
     if args.atomic_peak:
         print(json.dumps({"atomic_peak": atomic_peak(torch, lar)}), flush=True)
+        return
+    if args.philox_peak:
+        print(json.dumps({"philox_peak": philox_peak(torch, lar)}), flush=True)
         return
     if args.copy_floor:
         print(json.dumps({"copy_floor": copy_floor(torch, lar)}), flush=True)
@@ -610,6 +632,14 @@ def main():
                        "bound": "alu", "achieved": round(ach_all, 1),
                        "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s", "frac": round(ach_all / VALU_PEAK_GOPS, 4),
                        "avg_ms": round(t_all, 5)}
+    # the per-bin draw alone (Philox block + uniform), measured live: the
+    # floor of any per-bin counter-based sampler for this event's bins
+    pp = philox_peak(torch, lar, reps=10)
+    floor_ms = bins / pp["blocks_per_s"] * 1e3
+    draw_floor = {"probe": "lar_philox_probe (one Philox4x32-10 block + 52-bit uniform per bin)",
+                  "blocks_per_s": round(pp["blocks_per_s"], 1), "bins": bins, "floor_ms": round(floor_ms, 5),
+                  "frac_raster_main": round(floor_ms / per["raster"], 4),
+                  "frac_raster_all": round(floor_ms / t_all, 4)}
     fft_ms = per["r2c"] + per["wire"] + per["c2r"]
     fft_b = nbytes["r2c"] + nbytes["wire"] + nbytes["c2r"]
     roof_fft_all = {"kernels": "k_r2c_rows + k_wire_static + k_c2r_rows", "bound": "hbm",
@@ -637,6 +667,7 @@ def main():
         "host_wall_s": round(host_s, 4),
         "roofline": roof,
         "roofline_raster_all": roof_raster_all,
+        "raster_draw_floor": draw_floor,
         "roofline_fft_all": roof_fft_all,
         "roofline_fft": fft_roof,
     }

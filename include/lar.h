@@ -468,6 +468,16 @@ int lar_set_stage_events(void *const *events, int32_t n_events);
  * misaligned buf, n_floats < 64 or n_segments < 0. */
 int lar_atomic_probe(float *buf, int64_t n_floats, int64_t n_segments, void *stream);
 
+/* Measurement aid (no paper counterpart): the rate of the raster's per-bin
+ * draw, one Philox4x32-10 block and its 52-bit uniform, for comparing the
+ * raster kernels against it.  n_threads threads (a positive multiple of 256)
+ * draw the blocks of counters (i, 0x5EED, i >> 32, 0), i < n_blocks, under
+ * a fixed key, thread t taking i = t, t + n_threads, ...; out[t] (device,
+ * n_threads doubles) receives the sum of thread t's first uniforms.
+ * Asynchronous on stream.  LAR_EINVAL for a null or misaligned out,
+ * n_threads not a positive multiple of 256, or n_blocks < 0. */
+int lar_philox_probe(double *out, int64_t n_threads, int64_t n_blocks, void *stream);
+
 /* Measurement aid (no paper counterpart): the memory floor of the time
  * R2C's access pattern, for comparing that transform against it.  Copies
  * n_rows rows with the transform's persistent grid (blocks_per_cu

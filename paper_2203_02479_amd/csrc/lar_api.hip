@@ -14,6 +14,8 @@ using namespace lar;
 namespace lar {
 // probe_kernels.hip: n_seg scattered 64-float atomic segments into buf.
 hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipStream_t s);
+// probe_kernels.hip: Philox blocks and uniforms, one sum per thread.
+hipError_t launch_philox_probe(double* out, int64_t n_threads, int64_t n_blocks, hipStream_t s);
 // probe_kernels.hip: the time R2C's row access pattern without the transform.
 hipError_t launch_row_copy_probe(const float* in, int64_t ld_in, int n_in, int nrows, float2* out, int64_t ld_out,
                                  int n_out, int per_cu, hipStream_t s);
@@ -108,6 +110,14 @@ int lar_last_hip_error(void) { return g_last_hip; }
 int lar_atomic_probe(float* buf, int64_t n_floats, int64_t n_segments, void* stream) {
     if (!buf || n_floats < 64 || n_segments < 0 || reinterpret_cast<uintptr_t>(buf) % 256) return LAR_EINVAL;
     LAR_TRY(launch_atomic_probe(buf, n_floats, n_segments, (hipStream_t)stream));
+    return LAR_OK;
+}
+
+int lar_philox_probe(double* out, int64_t n_threads, int64_t n_blocks, void* stream) {
+    if (!out || n_threads < 256 || n_threads % 256 || n_threads / 256 > INT_MAX || n_blocks < 0 ||
+        reinterpret_cast<uintptr_t>(out) % 8)
+        return LAR_EINVAL;
+    LAR_TRY(launch_philox_probe(out, n_threads, n_blocks, (hipStream_t)stream));
     return LAR_OK;
 }
 

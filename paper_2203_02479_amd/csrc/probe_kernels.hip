@@ -7,6 +7,9 @@
 //                  segment at a slot spread over the buffer by a
 //                  multiplicative hash, so the requests land on every L2
 //                  channel and memory page the way scattered tile flushes do.
+//  k_philox_probe  the rate of the raster's per-bin draw: Philox4x32-10
+//                  blocks and their 52-bit uniforms, independent per thread,
+//                  summed so that none is skipped.
 //  k_row_copy_probe  the memory floor of the time R2C's access pattern: the
 //                  same persistent grid of 384-thread workgroups, rows read
 //                  as float pairs with the next row's loads in flight, rows
@@ -38,6 +41,26 @@ hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipS
     const int64_t blocks = (n_seg + 3) / 4, cap = 64 * (int64_t)device_cus();
     hipLaunchKernelGGL(k_atomic_probe, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, s, buf, slots,
                        n_seg);
+    return hipGetLastError();
+}
+
+// Thread t draws blocks i = t, t + T, ... < n_blocks (T threads in all),
+// each from the counter (i, 0x5EED, 0, 0) under a fixed key, and writes the
+// sum of their first uniforms to out[t].
+__global__ __launch_bounds__(256) void k_philox_probe(double* __restrict__ out, int64_t n_blocks) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x, T = (int64_t)gridDim.x * 256;
+    double acc = 0.0;
+    for (int64_t i = t; i < n_blocks; i += T) {
+        uint32_t c0 = (uint32_t)i, c1 = 0x5EEDu, c2 = (uint32_t)(i >> 32), c3 = 0u;
+        philox4x32_10(c0, c1, c2, c3, 0x12345678u, 0x9ABCDEF0u);
+        acc += u52(c0, c1);
+    }
+    out[t] = acc;
+}
+
+hipError_t launch_philox_probe(double* out, int64_t n_threads, int64_t n_blocks, hipStream_t s) {
+    if (n_threads <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_probe, dim3((unsigned)(n_threads / 256)), dim3(256), 0, s, out, n_blocks);
     return hipGetLastError();
 }
 

@@ -111,6 +111,7 @@ SIGNATURES = {
     "lar_set_stage_events": ([_P(_VP), ctypes.c_int32], ctypes.c_int),
     "lar_depos_nonfinite": ([_P(lar_depos), _VP, _VP], ctypes.c_int),
     "lar_atomic_probe": ([_VP, ctypes.c_int64, ctypes.c_int64, _VP], ctypes.c_int),
+    "lar_philox_probe": ([_VP, ctypes.c_int64, ctypes.c_int64, _VP], ctypes.c_int),
     "lar_row_copy_probe": ([_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_int64, ctypes.c_int32,
                             ctypes.c_int32, _VP], ctypes.c_int),
     "lar_schedule_default": ([_P(lar_plane), _P(lar_schedule)], ctypes.c_int),
@@ -236,6 +237,15 @@ def atomic_probe(buf, n_segments, stream=None):
     if buf.dtype != torch.float32:
         raise TypeError("float32 buffer expected")
     _check(_lib().lar_atomic_probe(_ptr(buf), buf.numel(), int(n_segments), _stream(stream)), "lar_atomic_probe")
+
+
+def philox_probe(out, n_blocks, stream=None):
+    """Rate probe of the raster's per-bin draw: out (float64 device tensor,
+    a multiple of 256 entries, one per thread) receives each thread's sum of
+    the first uniforms of its Philox blocks, n_blocks blocks in all."""
+    if out.dtype != torch.float64:
+        raise TypeError("float64 output expected")
+    _check(_lib().lar_philox_probe(_ptr(out), out.numel(), int(n_blocks), _stream(stream)), "lar_philox_probe")
 
 
 def row_copy_probe(src, dst, n_out, blocks_per_cu=2, stream=None):

@@ -179,6 +179,16 @@ def test_atomic_probe_host_side_errors(lar):
     assert L.lar_atomic_probe(al, 64, -1, None) == lar.LAR_EINVAL
 
 
+def test_philox_probe_host_side_errors(lar):
+    L = lar.lib()
+    a = ctypes.c_void_p(256)
+    assert L.lar_philox_probe(None, 256, 10, None) == lar.LAR_EINVAL
+    assert L.lar_philox_probe(ctypes.c_void_p(260), 256, 10, None) == lar.LAR_EINVAL
+    for n_threads in (0, 255, 257, -256):
+        assert L.lar_philox_probe(a, n_threads, 10, None) == lar.LAR_EINVAL
+    assert L.lar_philox_probe(a, 256, -1, None) == lar.LAR_EINVAL
+
+
 def test_row_copy_probe_host_side_errors(lar):
     L = lar.lib()
     a = ctypes.c_void_p(256)

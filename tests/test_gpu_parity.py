@@ -138,6 +138,22 @@ def test_atomic_probe_counts():
     torch.cuda.synchronize()
 
 
+def test_philox_probe_sums():
+    """The Philox rate probe's per-thread sums equal the oracle's Philox4x32-10
+    uniforms of the same counters, added in the same order (bit-exact)."""
+    torch, lar = _torch(), _lar()
+    n_threads, n_blocks = 512, 3001
+    out = torch.full((n_threads,), -1.0, dtype=torch.float64, device="cuda")
+    lar.philox_probe(out, n_blocks)
+    torch.cuda.synchronize()
+    ref = np.zeros(n_threads)
+    key = [0x12345678, 0x9ABCDEF0]
+    for i in range(n_blocks):
+        o = oracle.philox([i & 0xFFFFFFFF, 0x5EED, i >> 32, 0], key)
+        ref[i % n_threads] += oracle.u53(o[0], o[1])
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
 @pytest.mark.parametrize("rows,n_in,n_out,per_cu", [(1, 6000, 3073, 1), (37, 6000, 3073, 2), (600, 1024, 513, 3),
                                                     (5, 6144, 3073, 4)])
 def test_row_copy_probe_rows(rows, n_in, n_out, per_cu):
