@@ -45,8 +45,8 @@ hipError_t launch_atomic_probe(float* buf, int64_t n_floats, int64_t n_seg, hipS
 }
 
 // Thread t draws blocks i = t, t + T, ... < n_blocks (T threads in all),
-// each from the counter (i, 0x5EED, 0, 0) under a fixed key, and writes the
-// sum of their first uniforms to out[t].
+// each from the counter (i mod 2^32, 0x5EED, i >> 32, 0) under a fixed key,
+// and writes the sum of their first uniforms to out[t].
 __global__ __launch_bounds__(256) void k_philox_probe(double* __restrict__ out, int64_t n_blocks) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x, T = (int64_t)gridDim.x * 256;
     double acc = 0.0;
