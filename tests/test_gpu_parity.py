@@ -197,6 +197,8 @@ FFT_CASES = [
     dict(n_wires=21, n_ticks=6000, n_imp=10, nt_fft=6144, nw_fft=512),
     dict(n_wires=3, n_ticks=2, n_imp=1, nt_fft=2, nw_fft=3),
     dict(n_wires=10, n_ticks=16000, n_imp=2, nt_fft=16384, nw_fft=16),
+    dict(n_wires=1000, n_ticks=64, n_imp=2, nt_fft=64, nw_fft=1024),    # the largest wire FFT accepted
+    dict(n_wires=8, n_ticks=96, n_imp=40, nt_fft=96, nw_fft=12),        # many impact offsets per wire
 ]
 
 
