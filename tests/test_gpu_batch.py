@@ -138,6 +138,37 @@ def test_batch_waves_of_unequal_size():
         b.close()
 
 
+def test_batch_single_wave():
+    """One plane type in one wave (one grid region, the FFT stages still on
+    the plan's second stream): exact waveforms, graph and eager, run twice."""
+    import torch
+    from paper_2203_02479_amd import lar
+    planes = [inputs.Plane(n_wires=24, n_ticks=700, kind="unipolar")]
+    resps = [lar.spectrum_from_time(planes[0], inputs.response_time(planes[0].n_imp, planes[0].half_w, 200,
+                                                                    planes[0].kind))]
+    items, deps, off, woff = [], [], 0, 0
+    for i in range(4):
+        d = inputs.random_depos(planes[0], 900 + 50 * i, seed=700 + i, margin=0.1)
+        items.append((0, i, 2, off, len(d.q), woff))
+        deps.append(d)
+        off += len(d.q)
+        woff += planes[0].n_wires * planes[0].n_ticks
+    cat = inputs.Depos(*(np.concatenate([d.arrays()[k] for d in deps]) for k in range(5)))
+    fl = (1, 99, 0, 0)
+    ref = _reference(torch, lar, planes, resps, items, deps, fl, woff)
+    D = lar.DeviceDepos.from_host(cat)
+    for use_graph in (True, False):
+        wave = torch.full((woff,), -7.0, device="cuda")
+        ws = lar.workspace(lar.batch_workspace(planes, items, fl))
+        b = lar.Batch(planes, resps, D, 3.0, fl, items, wave, ws, use_graph=use_graph)
+        assert b.waves() == (1, 4)
+        b.run()
+        b.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(wave.cpu().numpy(), ref), use_graph
+        b.close()
+
+
 def test_batch_with_empty_items_and_one_item():
     torch, lar, planes, resps, items, deps, cat, fl, total = _setup(n_events=2, sizes=[0, 1500, 0, 700, 0, 0])
     D = lar.DeviceDepos.from_host(cat)
